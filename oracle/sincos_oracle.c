@@ -1,0 +1,527 @@
+/*
+ * sincos_oracle.c -- CPU oracle for the single-precision sine-cosine pair of
+ * M. H. Mendenhall, "A Fast, Vectorizable Algorithm for Producing
+ * Single-Precision Sine-Cosine Pairs" (2004).
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The GPU library
+ * shares no code, header, table or constant with it; its constants are typed
+ * here again from the paper's decimals.
+ *
+ * What it computes, one element at a time, in binary32 with round-to-nearest
+ * and IEEE subnormals, in the order the paper gives the steps:
+ *   1. scale the angle by 1/(2 pi) and reduce it modulo 1 by rounding to the
+ *      nearest integer and subtracting (Sec. II, opening paragraph);
+ *   2. the odd series for sin and the even series for cos of the quarter
+ *      angle, Horner in q^2 (Sec. II, polynomials of method 1 and method 2);
+ *   3. two angle doublings with the stable form, eq. (1);
+ *   4. the magnitude correction (Sec. II, discussion after the stability
+ *      analysis).  The factor is taken after the first doubling and applied
+ *      to the final pair, as the sample implementation of Fig. 1 does:
+ *      method 1 uses 2 - s^2 - c^2, method 2 the reciprocal of s^2 + c^2.
+ *
+ * Two arithmetic modes, selected per call:
+ *   ORACLE_FUSED  each multiply-add of the AltiVec form of Fig. 1 is one fused
+ *                 operation with a single rounding (C99 fmaf);
+ *   ORACLE_SPLIT  the same expression tree with every product and every sum
+ *                 rounded on its own.  This file must be compiled with
+ *                 -ffp-contract=off so that the compiler fuses nothing.
+ *
+ * Readings where the paper leaves a choice open:
+ *   - The listing adds +0.0 to every plain product because AltiVec has no
+ *     plain multiply.  Here a product is a product.  The two differ only in
+ *     the sign of an exact-zero result; the reduced angle below is never -0
+ *     (x1 - rint(x1) with round-to-nearest gives +0), so the pair is the same.
+ *   - rint() rounds ties to even, as vec_round does; q1 lies in [-1/2, 1/2].
+ *   - The negative multiply-subtract c - a*b is IEEE fusedMultiplyAdd(-a,b,c)
+ *     in the fused mode; its exact-zero result is +0.
+ *   - Method 2's coefficient ss2 is the value printed in the text of Sec. II
+ *     (-0.6466386936); the listing's -0.6466386396 is taken as a typo.
+ *   - Method 2's reciprocal is the correctly rounded 1.0f / d.
+ *   - Inputs with |x| >= 2^23 / (1/(2 pi)) reduce to q1 = 0 and give (0, 1);
+ *     +-Inf and NaN give (NaN, NaN).  Nothing here special-cases them.
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fPIC -shared
+ *        -pthread sincos_oracle.c -lm
+ */
+#define _GNU_SOURCE
+#include <fenv.h>
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_FUSED 0
+#define ORACLE_SPLIT 1
+#define ORACLE_METHOD1 0 /* normalized least-squares series + 2 - |p|^2 fix */
+#define ORACLE_METHOD2 1 /* arctan-fit series + reciprocal of |p|^2 */
+
+/* ---------------------------------------------------------------------- */
+/* Constants: the paper's decimals, each read as a C double and rounded to
+ * binary32 once, as the (vector float)(double) casts of Fig. 1 do.         */
+
+static float reduction_constant(void)
+{
+    /* 1/(2 pi) with pi written to ten decimals (Fig. 1). */
+    return (float)(1.0 / (2.0 * 3.1415926536));
+}
+
+struct series_coeffs {
+    float ss1, ss2, ss3, ss4; /* sin(pi q / 2) = q (ss1 + ss2 q^2 + ss3 q^4 + ss4 q^6) */
+    float cc1, cc2, cc3;      /* cos(pi q / 2) = 1 + cc1 q^2 + cc2 q^4 + cc3 q^6       */
+};
+
+static struct series_coeffs method_coeffs(int method)
+{
+    struct series_coeffs k;
+    if (method == ORACLE_METHOD2) {
+        /* Sec. II, second method: fit of the angle, not of the magnitude. */
+        k.ss1 = (float)1.5707963268;
+        k.ss2 = (float)-0.6466386936;
+        k.ss3 = (float)0.0679105987;
+        k.ss4 = (float)-0.0011573807;
+        k.cc1 = (float)-1.2341299769;
+        k.cc2 = (float)0.2465220241;
+        k.cc3 = (float)-0.0123926179;
+    } else {
+        /* Sec. II, first method: least-squares series of sin and cos. */
+        k.ss1 = (float)1.5707963235;
+        k.ss2 = (float)-0.645963615;
+        k.ss3 = (float)0.0796819754;
+        k.ss4 = (float)-0.0046075748;
+        k.cc1 = (float)-1.2336977925;
+        k.cc2 = (float)0.2536086171;
+        k.cc3 = (float)-0.0204391631;
+    }
+    return k;
+}
+
+/* ---------------------------------------------------------------------- */
+/* The two ways of evaluating a*b + c and c - a*b.                          */
+
+static float mul_add(float a, float b, float c, int arith)
+{
+    if (arith == ORACLE_FUSED)
+        return fmaf(a, b, c);
+    float p = a * b;
+    return p + c;
+}
+
+static float mul_sub_from(float a, float b, float c, int arith)
+{
+    if (arith == ORACLE_FUSED)
+        return fmaf(-a, b, c);
+    float p = a * b;
+    return c - p;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Step 1 (Sec. II): x1 = x / (2 pi); q1 = x1 - nearest integer to x1.
+ * The subtraction is exact (Sterbenz), so both modes agree.               */
+float oracle_reduce(float x)
+{
+    float x1 = x * reduction_constant();
+    float r = rintf(x1);
+    return x1 - r;
+}
+
+/* Step 2 (Sec. II polynomials): s1 ~ sin(pi q1 / 2), c1 ~ cos(pi q1 / 2). */
+void oracle_quarter_series(float q1, int arith, int method, float *s1, float *c1)
+{
+    struct series_coeffs k = method_coeffs(method);
+    float q2 = q1 * q1;
+
+    float t = mul_add(q2, k.ss4, k.ss3, arith);
+    t = mul_add(q2, t, k.ss2, arith);
+    t = mul_add(q2, t, k.ss1, arith);
+    *s1 = q1 * t;
+
+    float u = mul_add(q2, k.cc3, k.cc2, arith);
+    u = mul_add(q2, u, k.cc1, arith);
+    *c1 = mul_add(q2, u, 1.0f, arith);
+}
+
+/* Step 3, eq. (1): sin 2a = 2 sin a cos a, cos 2a = cos^2 a - sin^2 a.    */
+void oracle_double_angle(float s, float c, int arith, float *s_out, float *c_out)
+{
+    float cc = c * c;
+    *c_out = mul_sub_from(s, s, cc, arith);
+    float sc = s * c;
+    *s_out = 2.0f * sc;
+}
+
+/* Step 4: magnitude factor from the pair after the first doubling.  If that
+ * pair has squared magnitude 1 + e, the final pair has magnitude ~ 1 + e,
+ * and the factor is ~ 1 - e.                                               */
+float oracle_magnitude_factor(float s2, float c2, int arith, int method)
+{
+    if (method == ORACLE_METHOD2) {
+        float cc = c2 * c2;
+        float d = mul_add(s2, s2, cc, arith);
+        return 1.0f / d;
+    }
+    float inner = mul_sub_from(c2, c2, 2.0f, arith);
+    return mul_sub_from(s2, s2, inner, arith);
+}
+
+/* Steps 2-4 on an already reduced angle q1 in [-1/2, 1/2].                 */
+void oracle_pair_from_reduced(float q1, int arith, int method, float *s, float *c)
+{
+    float s1, c1, s2, c2, s3, c3;
+    oracle_quarter_series(q1, arith, method, &s1, &c1);
+    oracle_double_angle(s1, c1, arith, &s2, &c2);
+    float m = oracle_magnitude_factor(s2, c2, arith, method);
+    oracle_double_angle(s2, c2, arith, &s3, &c3);
+    *s = s3 * m;
+    *c = c3 * m;
+}
+
+/* Steps 1-4: the sine-cosine pair of the angle x (radians).               */
+void oracle_sincos_pair(float x, int arith, int method, float *s, float *c)
+{
+    oracle_pair_from_reduced(oracle_reduce(x), arith, method, s, c);
+}
+
+/* Same pair without step 4 (the drifted magnitude the fix removes).        */
+void oracle_pair_unfixed(float q1, int arith, int method, float *s, float *c)
+{
+    float s1, c1, s2, c2;
+    oracle_quarter_series(q1, arith, method, &s1, &c1);
+    oracle_double_angle(s1, c1, arith, &s2, &c2);
+    oracle_double_angle(s2, c2, arith, s, c);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Array drivers.  A plain loop over elements; with threads > 1 the array is
+ * cut into contiguous chunks, each run by the same scalar loop.  Each worker
+ * first installs the default floating-point environment (round to nearest,
+ * no flush-to-zero), whatever the host process has set.                    */
+
+typedef void (*chunk_fn)(void *job, int64_t lo, int64_t hi);
+
+struct chunk_task {
+    chunk_fn fn;
+    void *job;
+    int64_t lo, hi;
+};
+
+static void *chunk_worker(void *arg)
+{
+    struct chunk_task *t = (struct chunk_task *)arg;
+    fenv_t saved;
+    fegetenv(&saved);
+    fesetenv(FE_DFL_ENV);
+    t->fn(t->job, t->lo, t->hi);
+    fesetenv(&saved);
+    return NULL;
+}
+
+static int run_chunks(chunk_fn fn, void *job, int64_t n, int threads)
+{
+    if (threads < 1)
+        threads = 1;
+    if (threads > 256)
+        threads = 256;
+    if ((int64_t)threads > n)
+        threads = n > 0 ? (int)n : 1;
+    struct chunk_task tasks[256];
+    pthread_t tid[256];
+    int64_t per = (n + threads - 1) / threads;
+    int started = 0;
+    for (int i = 0; i < threads; i++) {
+        int64_t lo = (int64_t)i * per, hi = lo + per;
+        if (lo > n)
+            lo = n;
+        if (hi > n)
+            hi = n;
+        tasks[i].fn = fn;
+        tasks[i].job = job;
+        tasks[i].lo = lo;
+        tasks[i].hi = hi;
+    }
+    if (threads == 1) {
+        chunk_worker(&tasks[0]);
+        return 0;
+    }
+    for (int i = 0; i < threads; i++) {
+        if (pthread_create(&tid[i], NULL, chunk_worker, &tasks[i]) != 0)
+            break;
+        started++;
+    }
+    for (int i = started; i < threads; i++) /* could not start: run here */
+        chunk_worker(&tasks[i]);
+    for (int i = 0; i < started; i++)
+        pthread_join(tid[i], NULL);
+    return 0;
+}
+
+struct pair_job {
+    const float *x;
+    float *s, *c;
+    int arith, method;
+};
+
+static void pair_chunk(void *job, int64_t lo, int64_t hi)
+{
+    struct pair_job *j = (struct pair_job *)job;
+    for (int64_t i = lo; i < hi; i++)
+        oracle_sincos_pair(j->x[i], j->arith, j->method, &j->s[i], &j->c[i]);
+}
+
+/* s[i], c[i] = pair(x[i]) for 0 <= i < n.                                  */
+int oracle_sincos_f32(const float *x, float *s, float *c, int64_t n, int arith, int method,
+                      int threads)
+{
+    if (n < 0 || (n > 0 && (!x || !s || !c)))
+        return -1;
+    struct pair_job j = {x, s, c, arith, method};
+    return run_chunks(pair_chunk, &j, n, threads);
+}
+
+/* Pair from already reduced angles (the reduced-angle error sweep).        */
+struct reduced_job {
+    const float *q;
+    float *s, *c;
+    int arith, method, fixed;
+};
+
+static void reduced_chunk(void *job, int64_t lo, int64_t hi)
+{
+    struct reduced_job *j = (struct reduced_job *)job;
+    for (int64_t i = lo; i < hi; i++) {
+        if (j->fixed)
+            oracle_pair_from_reduced(j->q[i], j->arith, j->method, &j->s[i], &j->c[i]);
+        else
+            oracle_pair_unfixed(j->q[i], j->arith, j->method, &j->s[i], &j->c[i]);
+    }
+}
+
+int oracle_pair_from_reduced_f32(const float *q, float *s, float *c, int64_t n, int arith,
+                                 int method, int fixed, int threads)
+{
+    if (n < 0 || (n > 0 && (!q || !s || !c)))
+        return -1;
+    struct reduced_job j = {q, s, c, arith, method, fixed};
+    return run_chunks(reduced_chunk, &j, n, threads);
+}
+
+/* Reduction alone, elementwise.                                             */
+int oracle_reduce_f32(const float *x, float *q, int64_t n)
+{
+    if (n < 0 || (n > 0 && (!x || !q)))
+        return -1;
+    for (int64_t i = 0; i < n; i++)
+        q[i] = oracle_reduce(x[i]);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Error statistics against the double-precision system library, measured
+ * as the paper measures them (Sec. II, method 1 results):
+ *   vector error    sqrt((c - cos)^2 + (s - sin)^2)
+ *   amplitude error |1 - sqrt(c^2 + s^2)|
+ * over every binary32 reduced angle q whose bit pattern lies in
+ * [bits_lo, bits_hi] with the given stride, the reference angle being
+ * 2 pi q in double precision.  Negative q follow by symmetry.              */
+
+struct err_stats {
+    double max_vec, sum_sq_vec, max_amp;
+    float argmax_vec, argmax_amp;
+    int64_t count;
+};
+
+struct scan_job {
+    uint32_t bits_lo, bits_hi, stride;
+    int arith, method, fixed;
+    struct err_stats *per_chunk; /* one slot per chunk start */
+    int64_t per;                 /* chunk length, to find the slot */
+};
+
+static void scan_chunk(void *job, int64_t lo, int64_t hi)
+{
+    struct scan_job *j = (struct scan_job *)job;
+    struct err_stats st = {0.0, 0.0, 0.0, 0.0f, 0.0f, 0};
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int64_t k = lo; k < hi; k++) {
+        uint32_t bits = j->bits_lo + (uint32_t)k * j->stride;
+        float q;
+        memcpy(&q, &bits, sizeof q);
+        float s, c;
+        if (j->fixed)
+            oracle_pair_from_reduced(q, j->arith, j->method, &s, &c);
+        else
+            oracle_pair_unfixed(q, j->arith, j->method, &s, &c);
+        double a = two_pi * (double)q, rs, rc;
+        sincos(a, &rs, &rc);
+        double ds = (double)s - rs, dc = (double)c - rc;
+        double ev = sqrt(ds * ds + dc * dc);
+        double ea = fabs(1.0 - sqrt((double)s * s + (double)c * c));
+        st.sum_sq_vec += ev * ev;
+        if (ev > st.max_vec) {
+            st.max_vec = ev;
+            st.argmax_vec = q;
+        }
+        if (ea > st.max_amp) {
+            st.max_amp = ea;
+            st.argmax_amp = q;
+        }
+        st.count++;
+    }
+    j->per_chunk[lo / j->per] = st;
+}
+
+int oracle_error_scan_reduced(uint32_t bits_lo, uint32_t bits_hi, uint32_t stride, int arith,
+                              int method, int fixed, int threads, double *out_max_vec,
+                              double *out_rms_vec, double *out_max_amp, float *out_argmax_vec,
+                              float *out_argmax_amp, int64_t *out_count)
+{
+    if (stride == 0 || bits_hi < bits_lo)
+        return -1;
+    int64_t n = (int64_t)((bits_hi - bits_lo) / stride) + 1;
+    if (threads < 1)
+        threads = 1;
+    if (threads > 256)
+        threads = 256;
+    if ((int64_t)threads > n)
+        threads = (int)n;
+    struct err_stats slots[256];
+    memset(slots, 0, sizeof slots);
+    struct scan_job j = {bits_lo, bits_hi, stride, arith, method, fixed, slots,
+                         (n + threads - 1) / threads};
+    run_chunks(scan_chunk, &j, n, threads);
+    struct err_stats tot = {0.0, 0.0, 0.0, 0.0f, 0.0f, 0};
+    for (int i = 0; i < threads; i++) {
+        tot.sum_sq_vec += slots[i].sum_sq_vec;
+        tot.count += slots[i].count;
+        if (slots[i].max_vec > tot.max_vec) {
+            tot.max_vec = slots[i].max_vec;
+            tot.argmax_vec = slots[i].argmax_vec;
+        }
+        if (slots[i].max_amp > tot.max_amp) {
+            tot.max_amp = slots[i].max_amp;
+            tot.argmax_amp = slots[i].argmax_amp;
+        }
+    }
+    *out_max_vec = tot.max_vec;
+    *out_rms_vec = tot.count ? sqrt(tot.sum_sq_vec / (double)tot.count) : 0.0;
+    *out_max_amp = tot.max_amp;
+    *out_argmax_vec = tot.argmax_vec;
+    *out_argmax_amp = tot.argmax_amp;
+    *out_count = tot.count;
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Adjoint of the pair (plain definition): d sin/dx = cos, d cos/dx = -sin,
+ * so the gradient reaching x is gx = gs * c - gc * s, each product and the
+ * difference rounded once in binary32.  A null gs or gc counts as zero.    */
+int oracle_sincos_backward_f32(const float *s, const float *c, const float *gs, const float *gc,
+                               float *gx, int64_t n)
+{
+    if (n < 0 || (n > 0 && (!s || !c || !gx)))
+        return -1;
+    for (int64_t i = 0; i < n; i++) {
+        float a = gs ? gs[i] * c[i] : 0.0f;
+        float b = gc ? gc[i] * s[i] : 0.0f;
+        gx[i] = a - b;
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Sinusoid model used for fitting (the application of Sec. II, second
+ * paragraph: least-squares fits need a smooth function).  In binary32:
+ *   theta_ik = fmaf(w_k, t_i, phi_k)
+ *   y_i      = sum over k = 0..K-1, in that order, acc = fmaf(A_k, s_ik, acc)
+ * with (s_ik, c_ik) the pair of theta_ik from steps 1-4.                   */
+
+struct sinusoid_job {
+    const float *t, *A, *w, *phi;
+    int32_t K;
+    float *y;
+    int arith, method;
+};
+
+static void sinusoid_chunk(void *job, int64_t lo, int64_t hi)
+{
+    struct sinusoid_job *j = (struct sinusoid_job *)job;
+    for (int64_t i = lo; i < hi; i++) {
+        float acc = 0.0f;
+        for (int32_t k = 0; k < j->K; k++) {
+            float theta = fmaf(j->w[k], j->t[i], j->phi[k]);
+            float s, c;
+            oracle_sincos_pair(theta, j->arith, j->method, &s, &c);
+            acc = fmaf(j->A[k], s, acc);
+        }
+        j->y[i] = acc;
+    }
+}
+
+int oracle_sinusoid_forward_f32(const float *t, int64_t N, const float *A, const float *w,
+                                const float *phi, int32_t K, float *y, int arith, int method,
+                                int threads)
+{
+    if (N < 0 || K < 0 || (N > 0 && (!t || !y)) || (K > 0 && (!A || !w || !phi)))
+        return -1;
+    struct sinusoid_job j = {t, A, w, phi, K, y, arith, method};
+    return run_chunks(sinusoid_chunk, &j, N, threads);
+}
+
+/* Gradients of L with dL/dy_i = g_i (g = y - y_obs for L = 1/2 sum r^2):
+ *   gA_k   = sum_i g_i s_ik
+ *   gphi_k = A_k sum_i g_i c_ik
+ *   gw_k   = A_k sum_i g_i c_ik t_i
+ * The pairs are the binary32 pairs of the binary32 theta_ik above; every
+ * product and sum after that is done in double precision, in index order.
+ * abs_* receive the same sums over absolute values of the terms, which bound
+ * the rounding error of any other summation order.                          */
+int oracle_sinusoid_adjoint_f64(const float *t, const float *g, int64_t N, const float *A,
+                                const float *w, const float *phi, int32_t K, double *gA,
+                                double *gw, double *gphi, double *abs_A, double *abs_w,
+                                double *abs_phi, int arith, int method)
+{
+    if (N < 0 || K < 0 || (N > 0 && (!t || !g)) || (K > 0 && (!A || !w || !phi)))
+        return -1;
+    for (int32_t k = 0; k < K; k++) {
+        double sa = 0, sp = 0, sw = 0, aa = 0, ap = 0, aw = 0;
+        for (int64_t i = 0; i < N; i++) {
+            float theta = fmaf(w[k], t[i], phi[k]);
+            float s, c;
+            oracle_sincos_pair(theta, arith, method, &s, &c);
+            double ts = (double)g[i] * s;
+            double tc = (double)g[i] * c;
+            double tw = tc * (double)t[i];
+            sa += ts;
+            sp += tc;
+            sw += tw;
+            aa += fabs(ts);
+            ap += fabs(tc);
+            aw += fabs(tw);
+        }
+        gA[k] = sa;
+        gphi[k] = (double)A[k] * sp;
+        gw[k] = (double)A[k] * sw;
+        if (abs_A)
+            abs_A[k] = aa;
+        if (abs_phi)
+            abs_phi[k] = fabs((double)A[k]) * ap;
+        if (abs_w)
+            abs_w[k] = fabs((double)A[k]) * aw;
+    }
+    return 0;
+}
+
+/* Constants as the oracle rounds them, for the bit-pattern test.           */
+void oracle_constants(int method, float *out8)
+{
+    struct series_coeffs k = method_coeffs(method);
+    out8[0] = reduction_constant();
+    out8[1] = k.ss1;
+    out8[2] = k.ss2;
+    out8[3] = k.ss3;
+    out8[4] = k.ss4;
+    out8[5] = k.cc1;
+    out8[6] = k.cc2;
+    out8[7] = k.cc3;
+}
