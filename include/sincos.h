@@ -1,0 +1,201 @@
+/*
+ * sincos.h -- C ABI of libmi355_sincos.so: the branch-free single-precision
+ * sine-cosine pair of M. H. Mendenhall, "A Fast, Vectorizable Algorithm for
+ * Producing Single-Precision Sine-Cosine Pairs" (2004), on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The pair (s, c) of an angle x (radians) is computed in binary32 by the
+ * paper's steps: x is scaled by 1/(2 pi) and reduced modulo 1 by rounding to
+ * the nearest integer (ties to even) and subtracting (Sec. II); odd and even
+ * series give sin and cos of a quarter of the reduced turn (Sec. II, the
+ * polynomials of the chosen method); two angle doublings use the stable form
+ * of eq. (1); the pair is finally multiplied by a magnitude factor taken after
+ * the first doubling (Sec. II, magnitude correction; Fig. 1).
+ *
+ * Conventions for every entry point:
+ *  - Array pointers are DEVICE pointers owned by the caller.  The library never
+ *    frees them and keeps no reference after the call returns (plans keep the
+ *    pointers they were created with; see below).  Host tables passed in
+ *    (segment lists, lengths) are copied before the call returns.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *    it asynchronously; no call synchronizes the stream.  A fault inside a
+ *    kernel is reported by the caller's next synchronization, not here.
+ *  - Arguments are checked on the host before anything is enqueued; on error
+ *    nothing is enqueued and the call returns a negative status, with a
+ *    message available from sincos_last_error() on the same thread.
+ *  - n == 0 is a valid no-op.  Arrays must be 4-byte aligned; any 4-byte
+ *    alignment works (a float4 body is used when x, s and c share their
+ *    offset modulo 16 bytes, scalar elements otherwise).
+ *  - In place: x == s or x == c is allowed (each element is read before its
+ *    outputs are written).  s == c, or any other overlap between x, s and c,
+ *    is rejected with SINCOS_EOVERLAP.
+ *  - Special values: +-Inf and NaN give (NaN, NaN).  |x| >= 2^23 * 2 pi
+ *    (~5.27e7) reduces to a zero angle and gives (0, 1) exactly: this is what
+ *    the binary32 sequence computes, not a correct sine.
+ */
+#ifndef MI355_SINCOS_H
+#define MI355_SINCOS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#ifndef SINCOS_API
+#define SINCOS_API __attribute__((visibility("default")))
+#endif
+
+typedef enum {
+    SINCOS_OK = 0,
+    SINCOS_EINVAL = -1,   /* bad size, null or misaligned pointer, bad option */
+    SINCOS_EOVERLAP = -2, /* forbidden aliasing between inputs and outputs    */
+    SINCOS_ENOMEM = -3,   /* a library-owned device or host buffer failed     */
+    SINCOS_EHIP = -4,     /* the HIP runtime returned an error                */
+    SINCOS_ENODEV = -5    /* no usable gfx950 device is current               */
+} sincos_status_t;
+
+/* Arithmetic of the multiply-adds.
+ * FUSED: each multiply-add of the paper's AltiVec form is one fused operation
+ *        (one rounding), as AltiVec's vector multiply-add is.  Default.
+ * SPLIT: every product and every sum is rounded on its own (the same
+ *        expression tree, built with floating-point contraction off).
+ * CONTRACT: the SPLIT expression tree compiled with contraction allowed; the
+ *        compiler may fuse any product into a following sum.  Results are
+ *        within 2^-20 (absolute, per component) of SPLIT.
+ * FUSED and SPLIT are bit-exact against the CPU oracle of the same mode. */
+typedef enum {
+    SINCOS_ARITH_FUSED = 0,
+    SINCOS_ARITH_SPLIT = 1,
+    SINCOS_ARITH_CONTRACT = 2
+} sincos_arith_t;
+
+/* Series and magnitude fix (Sec. II).
+ * NORMALIZED: the first method: least-squares series of sin and cos, factor
+ *             2 - s^2 - c^2.  Default.
+ * ARCTAN:     the second method: series fit to the angle only, factor
+ *             1 / (s^2 + c^2) by correctly rounded division. */
+typedef enum {
+    SINCOS_METHOD_NORMALIZED = 0,
+    SINCOS_METHOD_ARCTAN = 1
+} sincos_method_t;
+
+/* Launch shape (0 in a field = library default).
+ * block:  threads per workgroup, a multiple of 64 in [64, 1024].
+ * unroll: float4 per thread per loop trip (1, 2, 4 or 8).
+ * grid:   workgroups; 0 = enough to cover the array once (capped). */
+typedef struct {
+    int32_t block;
+    int32_t unroll;
+    int32_t grid;
+    int32_t reserved;
+} sincos_launch_t;
+
+/* ---------------------------------------------------------------------- */
+/* Plain form: s[i], c[i] = pair(x[i]) for 0 <= i < n (SoA outputs).
+ * Default arithmetic FUSED, method NORMALIZED, default launch shape.      */
+SINCOS_API int sincos_f32(const float *x, float *s, float *c, int64_t n, void *stream);
+
+/* Same with explicit arithmetic, method and launch shape (launch may be
+ * NULL).                                                                  */
+SINCOS_API int sincos_f32_ex(const float *x, float *s, float *c, int64_t n, int32_t arith, int32_t method,
+                  const sincos_launch_t *launch, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Ragged form: `count` independent arrays in ONE persistent kernel launch.
+ * segs[j] = {x_j, s_j, c_j} (device pointers), lens[j] >= 0 its length.
+ * Both tables are host memory, read before the call returns.  Each segment
+ * obeys the plain form's aliasing rules; in addition no output may overlap
+ * any other segment's input or output (inputs may be shared).
+ * The descriptor table is staged through library-owned pinned and device
+ * buffers (a small ring guarded by events), so the call must not be made
+ * while `stream` is being captured into a graph: use a plan for that.     */
+typedef struct {
+    const float *x;
+    float *s;
+    float *c;
+} sincos_seg_t;
+
+SINCOS_API int sincos_f32_ragged(const sincos_seg_t *segs, const int64_t *lens, int32_t count, void *stream);
+
+SINCOS_API int sincos_f32_ragged_ex(const sincos_seg_t *segs, const int64_t *lens, int32_t count,
+                         int32_t arith, int32_t method, const sincos_launch_t *launch,
+                         void *stream);
+
+/* Ragged plan: the segment table is validated and copied to device memory
+ * once (synchronously, on the current device); launching it is then a
+ * single kernel launch with no host work and no allocation, safe to capture
+ * in a HIP graph.  The plan keeps the segment pointers: the caller keeps the
+ * arrays alive and may change their contents (not their addresses) between
+ * launches.  A plan is used from one thread at a time.                    */
+typedef struct sincos_ragged_plan sincos_ragged_plan_t;
+
+SINCOS_API int sincos_ragged_plan_create(const sincos_seg_t *segs, const int64_t *lens, int32_t count,
+                              int32_t arith, int32_t method, const sincos_launch_t *launch,
+                              sincos_ragged_plan_t **out_plan);
+/* Enqueue the plan's kernel on `stream`. */
+SINCOS_API int sincos_ragged_plan_launch(const sincos_ragged_plan_t *plan, void *stream);
+/* Enqueue the plan as a HIP graph (built by stream capture of the kernel on
+ * the first call and instantiated once; later calls replay it).          */
+SINCOS_API int sincos_ragged_plan_graph_launch(sincos_ragged_plan_t *plan, void *stream);
+/* Shape the plan resolved to (any field may be NULL). */
+SINCOS_API int sincos_ragged_plan_info(const sincos_ragged_plan_t *plan, int32_t *block, int32_t *unroll,
+                            int32_t *grid, int64_t *units, int64_t *elements);
+/* Free the plan's device table and graph.  Waits for nothing: the caller
+ * makes sure no launch of the plan is still running.                      */
+SINCOS_API int sincos_ragged_plan_destroy(sincos_ragged_plan_t *plan);
+
+/* ---------------------------------------------------------------------- */
+/* Adjoint of the pair (d sin/dx = cos, d cos/dx = -sin, the analytic
+ * derivative evaluated with the approximated pair):
+ *     gx[i] = gs[i] * c[i] - gc[i] * s[i]
+ * each product and the difference rounded once in binary32.  gs or gc may
+ * be NULL (treated as zero; both NULL writes +0).  gx may alias gs or gc
+ * exactly; no other overlap with gx is allowed.                           */
+SINCOS_API int sincos_f32_backward(const float *s, const float *c, const float *gs, const float *gc,
+                        float *gx, int64_t n, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Sinusoid model for least-squares fitting (the smooth-derivative use the
+ * paper motivates in Sec. II):  y(t_i) = sum_k A_k sin(w_k t_i + phi_k).
+ * In binary32: theta_ik = fma(w_k, t_i, phi_k); y_i accumulates
+ * fma(A_k, s_ik, y_i) over k = 0..K-1 in order, starting from +0.  Uses
+ * FUSED arithmetic and the NORMALIZED method for the pair.
+ * t, y: [N] device arrays; A, w, phi: [K] device arrays.  K >= 0.         */
+SINCOS_API int sinusoid_f32_forward(const float *t, int64_t N, const float *A, const float *w,
+                         const float *phi, int32_t K, float *y, void *stream);
+
+/* Gradients of a loss L with dL/dy_i = g_i:
+ *     gA_k   = sum_i g_i s_ik
+ *     gphi_k = A_k sum_i g_i c_ik
+ *     gw_k   = A_k sum_i g_i c_ik t_i
+ * (for L = 1/2 sum (y_i - y_obs_i)^2, g = y - y_obs).  Partial sums are taken
+ * in binary32 per block of samples and combined in a fixed order, so the
+ * result is deterministic.  gA, gw, gphi: [K] device outputs.  workspace:
+ * device scratch of at least sinusoid_f32_backward_workspace_bytes(N, K)
+ * bytes, owned by the caller, not aliasing anything else.                */
+SINCOS_API int64_t sinusoid_f32_backward_workspace_bytes(int64_t N, int32_t K);
+SINCOS_API int sinusoid_f32_backward(const float *t, const float *g, int64_t N, const float *A,
+                          const float *w, const float *phi, int32_t K, float *gA, float *gw,
+                          float *gphi, void *workspace, int64_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Measurement helper: the same memory traffic as the plain form (read 4 B,
+ * write 8 B per element, float4 body, same launch shape) with no
+ * arithmetic: s[i] = x[i], c[i] = x[i].  Gives the measured bandwidth
+ * ceiling for the plain kernel.                                           */
+SINCOS_API int sincos_copy_ceiling_f32(const float *x, float *s, float *c, int64_t n,
+                            const sincos_launch_t *launch, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Message for the last non-OK status returned on this thread ("" if none). */
+SINCOS_API const char *sincos_last_error(void);
+
+/* Library version string. */
+SINCOS_API const char *sincos_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MI355_SINCOS_H */

@@ -1,0 +1,253 @@
+"""ctypes binding of libmi355_sincos.so (declared in include/sincos.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Array arguments may be torch tensors (float32, contiguous, on the
+GPU) or raw device addresses (int).  `stream` defaults to torch's current HIP
+stream.  A non-OK status raises SincosError with the library's message.
+If the shared library has not been built, loading it raises RuntimeError:
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmi355_sincos.so")
+
+OK, EINVAL, EOVERLAP, ENOMEM, EHIP, ENODEV = 0, -1, -2, -3, -4, -5
+ARITH_FUSED, ARITH_SPLIT, ARITH_CONTRACT = 0, 1, 2
+METHOD_NORMALIZED, METHOD_ARCTAN = 0, 1
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EOVERLAP", -3: "ENOMEM", -4: "EHIP", -5: "ENODEV"}
+
+
+class SincosError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s (%d): %s" % (STATUS_NAMES.get(status, "?"), status, message))
+        self.status = status
+        self.message = message
+
+
+class Launch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("unroll", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Seg(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("s", ctypes.c_void_p), ("c", ctypes.c_void_p)]
+
+
+_lock = threading.Lock()
+_lib = None
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+
+_SIGNATURES = {
+    "sincos_f32": (ctypes.c_int, [_P, _P, _P, _I64, _P]),
+    "sincos_f32_ex": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _I32, ctypes.POINTER(Launch), _P]),
+    "sincos_f32_ragged": (ctypes.c_int, [ctypes.POINTER(Seg), ctypes.POINTER(_I64), _I32, _P]),
+    "sincos_f32_ragged_ex": (ctypes.c_int, [ctypes.POINTER(Seg), ctypes.POINTER(_I64), _I32, _I32,
+                                            _I32, ctypes.POINTER(Launch), _P]),
+    "sincos_ragged_plan_create": (ctypes.c_int, [ctypes.POINTER(Seg), ctypes.POINTER(_I64), _I32,
+                                                 _I32, _I32, ctypes.POINTER(Launch),
+                                                 ctypes.POINTER(_P)]),
+    "sincos_ragged_plan_launch": (ctypes.c_int, [_P, _P]),
+    "sincos_ragged_plan_graph_launch": (ctypes.c_int, [_P, _P]),
+    "sincos_ragged_plan_info": (ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                               ctypes.POINTER(_I32), ctypes.POINTER(_I64),
+                                               ctypes.POINTER(_I64)]),
+    "sincos_ragged_plan_destroy": (ctypes.c_int, [_P]),
+    "sincos_f32_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P]),
+    "sinusoid_f32_forward": (ctypes.c_int, [_P, _I64, _P, _P, _P, _I32, _P, _P]),
+    "sinusoid_f32_backward_workspace_bytes": (ctypes.c_int64, [_I64, _I32]),
+    "sinusoid_f32_backward": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _P, _P, _P, _P, _I64,
+                                             _P]),
+    "sincos_copy_ceiling_f32": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(Launch), _P]),
+    "sincos_last_error": (ctypes.c_char_p, []),
+    "sincos_version": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """The loaded library (raises RuntimeError if it is not built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(
+                    "libmi355_sincos.so is not built (python -m paper_cs_0406049_amd.build); "
+                    "this package has no CPU or fallback path")
+            L = ctypes.CDLL(LIB_PATH)
+            for name, (res, args) in _SIGNATURES.items():
+                fn = getattr(L, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().sincos_last_error().decode()
+
+
+def _check(status: int) -> int:
+    if status != OK:
+        raise SincosError(status, last_error())
+    return status
+
+
+def _ptr(a):
+    """Device address of a tensor (float32, contiguous, on the GPU) or an int."""
+    if a is None:
+        return None
+    if isinstance(a, int):
+        return a
+    if not a.is_cuda:
+        raise ValueError("array must be on the GPU")
+    if a.dtype.itemsize != 4 or not a.is_floating_point():
+        raise ValueError("array must be float32")
+    if not a.is_contiguous():
+        raise ValueError("array must be contiguous")
+    return a.data_ptr()
+
+
+def _raw_ptr(a):
+    """Device address of a tensor of any dtype, an int, or None."""
+    if a is None or isinstance(a, int):
+        return a
+    if not a.is_cuda:
+        raise ValueError("array must be on the GPU")
+    return a.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _launch(launch):
+    if launch is None:
+        return None
+    if isinstance(launch, Launch):
+        return ctypes.byref(launch)
+    b, u, g = (tuple(launch) + (0, 0, 0))[:3]
+    return ctypes.byref(Launch(int(b), int(u), int(g), 0))
+
+
+def _numel(a, n):
+    if n is not None:
+        return int(n)
+    return int(a.numel())
+
+
+# ---------------------------------------------------------------------------
+# Entry points, same names as the C ABI.
+
+
+def sincos_f32(x, s, c, n=None, stream=None) -> None:
+    _check(lib().sincos_f32(_ptr(x), _ptr(s), _ptr(c), _numel(x, n), _stream(stream)))
+
+
+def sincos_f32_ex(x, s, c, n=None, arith=ARITH_FUSED, method=METHOD_NORMALIZED, launch=None,
+                  stream=None) -> None:
+    _check(lib().sincos_f32_ex(_ptr(x), _ptr(s), _ptr(c), _numel(x, n), int(arith), int(method),
+                               _launch(launch), _stream(stream)))
+
+
+def sincos_copy_ceiling_f32(x, s, c, n=None, launch=None, stream=None) -> None:
+    _check(lib().sincos_copy_ceiling_f32(_ptr(x), _ptr(s), _ptr(c), _numel(x, n),
+                                         _launch(launch), _stream(stream)))
+
+
+def _seg_tables(segs, lens):
+    count = len(segs)
+    st = (Seg * max(count, 1))()
+    lt = (_I64 * max(count, 1))()
+    for j, (x, s, c) in enumerate(segs):
+        st[j] = Seg(_ptr(x), _ptr(s), _ptr(c))
+        lt[j] = int(lens[j]) if lens is not None else int(x.numel())
+    return st, lt, count
+
+
+def sincos_f32_ragged(segs, lens=None, stream=None, arith=ARITH_FUSED, method=METHOD_NORMALIZED,
+                      launch=None) -> None:
+    """segs: sequence of (x, s, c); lens: lengths (default: x.numel())."""
+    st, lt, count = _seg_tables(segs, lens)
+    _check(lib().sincos_f32_ragged_ex(st, lt, count, int(arith), int(method), _launch(launch),
+                                      _stream(stream)))
+
+
+class RaggedPlan:
+    """A ragged batch validated and uploaded once; launch() or graph_launch()
+    then enqueue a single kernel (or its graph) with no host work."""
+
+    def __init__(self, segs, lens=None, arith=ARITH_FUSED, method=METHOD_NORMALIZED,
+                 launch=None):
+        st, lt, count = _seg_tables(segs, lens)
+        h = _P()
+        _check(lib().sincos_ragged_plan_create(st, lt, count, int(arith), int(method),
+                                               _launch(launch), ctypes.byref(h)))
+        self._h = h
+        self._keep = list(segs)  # the plan holds raw pointers: keep the arrays alive
+
+    def launch(self, stream=None):
+        _check(lib().sincos_ragged_plan_launch(self._h, _stream(stream)))
+
+    def graph_launch(self, stream=None):
+        _check(lib().sincos_ragged_plan_graph_launch(self._h, _stream(stream)))
+
+    def info(self):
+        b, u, g = _I32(), _I32(), _I32()
+        units, elems = _I64(), _I64()
+        _check(lib().sincos_ragged_plan_info(self._h, ctypes.byref(b), ctypes.byref(u),
+                                             ctypes.byref(g), ctypes.byref(units),
+                                             ctypes.byref(elems)))
+        return dict(block=b.value, unroll=u.value, grid=g.value, units=units.value,
+                    elements=elems.value)
+
+    def destroy(self):
+        if self._h:
+            lib().sincos_ragged_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def sincos_f32_backward(s, c, gs, gc, gx, n=None, stream=None) -> None:
+    _check(lib().sincos_f32_backward(_ptr(s), _ptr(c), _ptr(gs), _ptr(gc), _ptr(gx),
+                                     _numel(s, n), _stream(stream)))
+
+
+def sinusoid_f32_forward(t, A, w, phi, y, N=None, K=None, stream=None) -> None:
+    _check(lib().sinusoid_f32_forward(_ptr(t), _numel(t, N), _ptr(A), _ptr(w), _ptr(phi),
+                                      _numel(A, K), _ptr(y), _stream(stream)))
+
+
+def sinusoid_f32_backward_workspace_bytes(N: int, K: int) -> int:
+    return int(lib().sinusoid_f32_backward_workspace_bytes(int(N), int(K)))
+
+
+def sinusoid_f32_backward(t, g, A, w, phi, gA, gw, gphi, workspace, workspace_bytes=None,
+                          N=None, K=None, stream=None) -> None:
+    N = _numel(t, N)
+    K = _numel(A, K)
+    if workspace_bytes is None:
+        workspace_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _check(lib().sinusoid_f32_backward(_ptr(t), _ptr(g), N, _ptr(A), _ptr(w), _ptr(phi), K,
+                                       _ptr(gA), _ptr(gw), _ptr(gphi), _raw_ptr(workspace),
+                                       int(workspace_bytes), _stream(stream)))
+
+
+def version() -> str:
+    return lib().sincos_version().decode()

@@ -1,0 +1,690 @@
+// capi.cpp -- the C ABI of libmi355_sincos.so (declared in include/sincos.h):
+// argument checks, launch-shape resolution, descriptor staging for the ragged
+// form, ragged plans with graph replay, and error reporting.
+#include "../../include/sincos.h"
+#include "internal.hpp"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace mi355 {
+
+// ---------------------------------------------------------------------------
+// Errors
+
+static thread_local std::string g_last_error;
+
+int set_error(int status, const std::string &msg)
+{
+    g_last_error = msg;
+    return status;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+static int hip_error(hipError_t e, const char *what)
+{
+    return set_error(SINCOS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Device facts
+
+static std::mutex g_dev_mu;
+static std::map<int, std::unique_ptr<DeviceInfo>> g_devs;
+
+const DeviceInfo &device_info(int device)
+{
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    auto it = g_devs.find(device);
+    if (it != g_devs.end())
+        return *it->second;
+    auto info = std::make_unique<DeviceInfo>();
+    info->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        info->cus = prop.multiProcessorCount;
+        info->arch = prop.gcnArchName;
+        info->arch_ok = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    }
+    const DeviceInfo &ref = *info;
+    g_devs[device] = std::move(info);
+    return ref;
+}
+
+// The current device, checked to be a gfx950.
+static int current_device(const DeviceInfo **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return set_error(SINCOS_ENODEV, std::string("no HIP device: ") + hipGetErrorString(e));
+    const DeviceInfo &info = device_info(dev);
+    if (!info.arch_ok)
+        return set_error(SINCOS_ENODEV, "device " + std::to_string(dev) + " is " +
+                                             (info.arch.empty() ? "unknown" : info.arch) +
+                                             ", this library is built for gfx950 only");
+    *out = &info;
+    return SINCOS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launch shapes
+
+static int check_shape(const sincos_launch_t *req, LaunchShape *out)
+{
+    LaunchShape sh;
+    if (req) {
+        if (req->block != 0)
+            sh.block = req->block;
+        if (req->unroll != 0)
+            sh.unroll = req->unroll;
+        sh.grid = req->grid;
+    }
+    if (sh.block < 64 || sh.block > 1024 || sh.block % 64 != 0)
+        return set_error(SINCOS_EINVAL, "launch.block must be a multiple of 64 in [64, 1024]");
+    if (sh.unroll != 1 && sh.unroll != 2 && sh.unroll != 4 && sh.unroll != 8)
+        return set_error(SINCOS_EINVAL, "launch.unroll must be 1, 2, 4 or 8");
+    if (sh.grid < 0)
+        return set_error(SINCOS_EINVAL, "launch.grid must be >= 0");
+    *out = sh;
+    return SINCOS_OK;
+}
+
+LaunchShape resolve_plain_shape(const LaunchShape &req, int64_t, const DeviceInfo &)
+{
+    LaunchShape sh = req;
+    if (sh.grid <= 0 || sh.grid > (1 << 20))
+        sh.grid = 1 << 20;  // cover the array (grid-stride beyond this)
+    return sh;
+}
+
+LaunchShape resolve_ragged_shape(const LaunchShape &req, int64_t total_units,
+                                 const DeviceInfo &dev)
+{
+    LaunchShape sh = req;
+    if (sh.grid <= 0)
+        sh.grid = std::max(1, dev.cus) * 8;  // persistent: 8 workgroups per CU
+    sh.grid = (int)std::max<int64_t>(1, std::min<int64_t>(sh.grid, std::max<int64_t>(total_units, 1)));
+    return sh;
+}
+
+// ---------------------------------------------------------------------------
+// Argument checks
+
+static bool ranges_overlap(const void *a, int64_t na, const void *b, int64_t nb)
+{
+    const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+    return pa < pb + (uintptr_t)nb * 4 && pb < pa + (uintptr_t)na * 4;
+}
+
+static bool aligned4(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 3) == 0; }
+
+static int check_triplet(const float *x, const float *s, const float *c, int64_t n,
+                         const char *who)
+{
+    if (n < 0)
+        return set_error(SINCOS_EINVAL, std::string(who) + ": n < 0");
+    if (n == 0)
+        return SINCOS_OK;
+    if (!x || !s || !c)
+        return set_error(SINCOS_EINVAL, std::string(who) + ": null pointer with n > 0");
+    if (!aligned4(x) || !aligned4(s) || !aligned4(c))
+        return set_error(SINCOS_EINVAL, std::string(who) + ": pointers must be 4-byte aligned");
+    if (n > (int64_t(1) << 60))
+        return set_error(SINCOS_EINVAL, std::string(who) + ": n too large");
+    if (ranges_overlap(s, n, c, n))
+        return set_error(SINCOS_EOVERLAP, std::string(who) + ": s and c overlap");
+    if (x != s && ranges_overlap(x, n, s, n))
+        return set_error(SINCOS_EOVERLAP, std::string(who) + ": x partially overlaps s");
+    if (x != c && ranges_overlap(x, n, c, n))
+        return set_error(SINCOS_EOVERLAP, std::string(who) + ": x partially overlaps c");
+    return SINCOS_OK;
+}
+
+static int check_modes(int32_t arith, int32_t method)
+{
+    if (arith < 0 || arith > 2)
+        return set_error(SINCOS_EINVAL, "arith must be FUSED, SPLIT or CONTRACT");
+    if (method < 0 || method > 1)
+        return set_error(SINCOS_EINVAL, "method must be NORMALIZED or ARCTAN");
+    return SINCOS_OK;
+}
+
+// Cross-segment aliasing: outputs pairwise disjoint; an input may overlap an
+// output only as the exact in-place case of its own segment.
+struct Interval {
+    uintptr_t lo, hi;
+    int32_t seg;
+};
+
+static int check_ragged_aliasing(const sincos_seg_t *segs, const int64_t *lens, int32_t count)
+{
+    std::vector<Interval> outs;
+    outs.reserve((size_t)count * 2);
+    for (int32_t j = 0; j < count; ++j) {
+        if (lens[j] == 0)
+            continue;
+        const uintptr_t b = (uintptr_t)lens[j] * 4;
+        outs.push_back({reinterpret_cast<uintptr_t>(segs[j].s), reinterpret_cast<uintptr_t>(segs[j].s) + b, j});
+        outs.push_back({reinterpret_cast<uintptr_t>(segs[j].c), reinterpret_cast<uintptr_t>(segs[j].c) + b, j});
+    }
+    std::sort(outs.begin(), outs.end(), [](const Interval &a, const Interval &b) { return a.lo < b.lo; });
+    for (size_t i = 1; i < outs.size(); ++i)
+        if (outs[i].lo < outs[i - 1].hi)
+            return set_error(SINCOS_EOVERLAP, "ragged: outputs of segments " +
+                                                  std::to_string(outs[i - 1].seg) + " and " +
+                                                  std::to_string(outs[i].seg) + " overlap");
+    for (int32_t j = 0; j < count; ++j) {
+        if (lens[j] == 0)
+            continue;
+        const uintptr_t lo = reinterpret_cast<uintptr_t>(segs[j].x), hi = lo + (uintptr_t)lens[j] * 4;
+        auto it = std::lower_bound(outs.begin(), outs.end(), hi,
+                                   [](const Interval &a, uintptr_t v) { return a.lo < v; });
+        if (it == outs.begin())
+            continue;
+        --it;  // the output with the largest start below hi
+        if (it->hi <= lo)
+            continue;
+        if (!(it->seg == j && it->lo == lo))
+            return set_error(SINCOS_EOVERLAP, "ragged: input of segment " + std::to_string(j) +
+                                                  " overlaps an output of segment " +
+                                                  std::to_string(it->seg));
+    }
+    return SINCOS_OK;
+}
+
+static int check_ragged(const sincos_seg_t *segs, const int64_t *lens, int32_t count)
+{
+    if (count < 0)
+        return set_error(SINCOS_EINVAL, "ragged: count < 0");
+    if (count == 0)
+        return SINCOS_OK;
+    if (!segs || !lens)
+        return set_error(SINCOS_EINVAL, "ragged: null segment or length table");
+    for (int32_t j = 0; j < count; ++j) {
+        int rc = check_triplet(segs[j].x, segs[j].s, segs[j].c, lens[j], "ragged segment");
+        if (rc != SINCOS_OK)
+            return set_error(rc, g_last_error + " (segment " + std::to_string(j) + ")");
+    }
+    return check_ragged_aliasing(segs, lens, count);
+}
+
+// Host table of a ragged batch: descriptors of the non-empty segments, then
+// their first-unit offsets (count + 1 entries).
+struct RaggedTable {
+    std::vector<RaggedDesc> desc;
+    std::vector<int64_t> ubeg;
+    int64_t elements = 0;
+};
+
+static void build_table(const sincos_seg_t *segs, const int64_t *lens, int32_t count,
+                        const LaunchShape &sh, RaggedTable &t)
+{
+    t.desc.clear();
+    t.ubeg.clear();
+    t.elements = 0;
+    int64_t u = 0;
+    for (int32_t j = 0; j < count; ++j) {
+        if (lens[j] == 0)
+            continue;
+        RaggedDesc d = make_desc(segs[j].x, segs[j].s, segs[j].c, lens[j]);
+        t.desc.push_back(d);
+        t.ubeg.push_back(u);
+        u += ragged_units(d, sh);
+        t.elements += lens[j];
+    }
+    t.ubeg.push_back(u);
+}
+
+// ---------------------------------------------------------------------------
+// Staging ring for one-shot ragged calls: pinned host + device buffer per
+// slot, reused once the event recorded after its last use has completed.
+
+struct StageSlot {
+    char *host = nullptr;
+    char *dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+
+struct StageRing {
+    std::mutex mu;
+    std::vector<StageSlot> slots;
+    size_t next = 0;
+};
+
+static std::mutex g_ring_mu;
+static std::map<int, std::unique_ptr<StageRing>> g_rings;
+constexpr int kStageSlots = 8;
+
+static StageRing &ring_for(int device)
+{
+    std::lock_guard<std::mutex> lk(g_ring_mu);
+    auto &r = g_rings[device];
+    if (!r) {
+        r = std::make_unique<StageRing>();
+        r->slots.resize(kStageSlots);
+    }
+    return *r;
+}
+
+int ragged_enqueue(const RaggedTable &t, int arith, int method, const LaunchShape &shape,
+                   const DeviceInfo &dev, hipStream_t stream)
+{
+    const int32_t count = (int32_t)t.desc.size();
+    if (count == 0)
+        return SINCOS_OK;
+    const int64_t total = t.ubeg.back();
+    const LaunchShape sh = resolve_ragged_shape(shape, total, dev);
+    const size_t desc_bytes = sizeof(RaggedDesc) * (size_t)count;
+    const size_t bytes = desc_bytes + sizeof(int64_t) * (size_t)(count + 1);
+
+    StageRing &ring = ring_for(dev.device);
+    std::lock_guard<std::mutex> lk(ring.mu);
+    StageSlot &slot = ring.slots[ring.next];
+    ring.next = (ring.next + 1) % ring.slots.size();
+    hipError_t e;
+    if (slot.pending) {
+        e = hipEventSynchronize(slot.done);
+        if (e != hipSuccess)
+            return hip_error(e, "ragged: waiting for a staging slot");
+        slot.pending = false;
+    }
+    if (slot.cap < bytes) {
+        if (slot.host)
+            (void)hipHostFree(slot.host);
+        if (slot.dev)
+            (void)hipFree(slot.dev);
+        slot.host = nullptr;
+        slot.dev = nullptr;
+        slot.cap = 0;
+        size_t cap = std::max<size_t>(bytes, 64 * 1024);
+        if (hipHostMalloc((void **)&slot.host, cap, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc((void **)&slot.dev, cap) != hipSuccess) {
+            if (slot.host)
+                (void)hipHostFree(slot.host);
+            slot.host = nullptr;
+            slot.dev = nullptr;
+            return set_error(SINCOS_ENOMEM, "ragged: cannot allocate the staging buffers");
+        }
+        slot.cap = cap;
+    }
+    if (!slot.done && hipEventCreateWithFlags(&slot.done, hipEventDisableTiming) != hipSuccess)
+        return set_error(SINCOS_EHIP, "ragged: cannot create an event");
+    std::memcpy(slot.host, t.desc.data(), desc_bytes);
+    std::memcpy(slot.host + desc_bytes, t.ubeg.data(), sizeof(int64_t) * (size_t)(count + 1));
+    e = hipMemcpyAsync(slot.dev, slot.host, bytes, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess)
+        return hip_error(e, "ragged: staging copy");
+    e = launch_ragged(reinterpret_cast<const RaggedDesc *>(slot.dev),
+                      reinterpret_cast<const int64_t *>(slot.dev + desc_bytes), count, total, arith,
+                      method, sh, stream);
+    if (e != hipSuccess)
+        return hip_error(e, "ragged: kernel launch");
+    e = hipEventRecord(slot.done, stream);
+    if (e != hipSuccess)
+        return hip_error(e, "ragged: event record");
+    slot.pending = true;
+    return SINCOS_OK;
+}
+
+}  // namespace mi355
+
+using namespace mi355;
+
+// ---------------------------------------------------------------------------
+// Plain form
+
+extern "C" int sincos_f32_ex(const float *x, float *s, float *c, int64_t n, int32_t arith,
+                             int32_t method, const sincos_launch_t *launch, void *stream)
+{
+    clear_error();
+    int rc = check_triplet(x, s, c, n, "sincos_f32");
+    if (rc != SINCOS_OK)
+        return rc;
+    if ((rc = check_modes(arith, method)) != SINCOS_OK)
+        return rc;
+    LaunchShape sh;
+    if ((rc = check_shape(launch, &sh)) != SINCOS_OK)
+        return rc;
+    if (n == 0)
+        return SINCOS_OK;
+    const DeviceInfo *dev;
+    if ((rc = current_device(&dev)) != SINCOS_OK)
+        return rc;
+    hipError_t e = launch_sincos(x, s, c, n, arith, method, resolve_plain_shape(sh, n, *dev),
+                                 (hipStream_t)stream);
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "sincos_f32: kernel launch");
+}
+
+extern "C" int sincos_f32(const float *x, float *s, float *c, int64_t n, void *stream)
+{
+    return sincos_f32_ex(x, s, c, n, SINCOS_ARITH_FUSED, SINCOS_METHOD_NORMALIZED, nullptr,
+                         stream);
+}
+
+extern "C" int sincos_copy_ceiling_f32(const float *x, float *s, float *c, int64_t n,
+                                       const sincos_launch_t *launch, void *stream)
+{
+    clear_error();
+    int rc = check_triplet(x, s, c, n, "sincos_copy_ceiling_f32");
+    if (rc != SINCOS_OK)
+        return rc;
+    if (x == s || x == c)
+        return set_error(SINCOS_EOVERLAP, "sincos_copy_ceiling_f32: no in-place use");
+    const uintptr_t bits = reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(s) |
+                           reinterpret_cast<uintptr_t>(c);
+    if ((bits & 15) != 0 || n % 4 != 0)
+        return set_error(SINCOS_EINVAL,
+                         "sincos_copy_ceiling_f32: needs 16-byte aligned arrays and n % 4 == 0");
+    LaunchShape sh;
+    if ((rc = check_shape(launch, &sh)) != SINCOS_OK)
+        return rc;
+    if (n == 0)
+        return SINCOS_OK;
+    const DeviceInfo *dev;
+    if ((rc = current_device(&dev)) != SINCOS_OK)
+        return rc;
+    hipError_t e = launch_copy_ceiling(x, s, c, n, resolve_plain_shape(sh, n, *dev),
+                                       (hipStream_t)stream);
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "sincos_copy_ceiling_f32: kernel launch");
+}
+
+// ---------------------------------------------------------------------------
+// Ragged form
+
+extern "C" int sincos_f32_ragged_ex(const sincos_seg_t *segs, const int64_t *lens, int32_t count,
+                                    int32_t arith, int32_t method, const sincos_launch_t *launch,
+                                    void *stream)
+{
+    clear_error();
+    int rc = check_ragged(segs, lens, count);
+    if (rc != SINCOS_OK)
+        return rc;
+    if ((rc = check_modes(arith, method)) != SINCOS_OK)
+        return rc;
+    LaunchShape sh;
+    if ((rc = check_shape(launch, &sh)) != SINCOS_OK)
+        return rc;
+    if (count == 0)
+        return SINCOS_OK;
+    const DeviceInfo *dev;
+    if ((rc = current_device(&dev)) != SINCOS_OK)
+        return rc;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess &&
+        cs != hipStreamCaptureStatusNone)
+        return set_error(SINCOS_EINVAL,
+                         "sincos_f32_ragged: stream is being captured; use a ragged plan");
+    RaggedTable t;
+    build_table(segs, lens, count, sh, t);
+    return ragged_enqueue(t, arith, method, sh, *dev, (hipStream_t)stream);
+}
+
+extern "C" int sincos_f32_ragged(const sincos_seg_t *segs, const int64_t *lens, int32_t count,
+                                 void *stream)
+{
+    return sincos_f32_ragged_ex(segs, lens, count, SINCOS_ARITH_FUSED, SINCOS_METHOD_NORMALIZED,
+                                nullptr, stream);
+}
+
+struct sincos_ragged_plan {
+    int device = -1;
+    int arith = 0, method = 0;
+    LaunchShape shape;
+    int32_t count = 0;
+    int64_t total_units = 0;
+    int64_t elements = 0;
+    char *dev_buf = nullptr;
+    RaggedDesc *d_desc = nullptr;
+    int64_t *d_ubeg = nullptr;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" int sincos_ragged_plan_create(const sincos_seg_t *segs, const int64_t *lens,
+                                         int32_t count, int32_t arith, int32_t method,
+                                         const sincos_launch_t *launch,
+                                         sincos_ragged_plan_t **out_plan)
+{
+    clear_error();
+    if (!out_plan)
+        return set_error(SINCOS_EINVAL, "plan_create: null out_plan");
+    *out_plan = nullptr;
+    int rc = check_ragged(segs, lens, count);
+    if (rc != SINCOS_OK)
+        return rc;
+    if ((rc = check_modes(arith, method)) != SINCOS_OK)
+        return rc;
+    LaunchShape sh;
+    if ((rc = check_shape(launch, &sh)) != SINCOS_OK)
+        return rc;
+    const DeviceInfo *dev;
+    if ((rc = current_device(&dev)) != SINCOS_OK)
+        return rc;
+    RaggedTable t;
+    build_table(segs, lens, count, sh, t);
+    auto plan = std::make_unique<sincos_ragged_plan>();
+    plan->device = dev->device;
+    plan->arith = arith;
+    plan->method = method;
+    plan->count = (int32_t)t.desc.size();
+    plan->total_units = t.ubeg.back();
+    plan->elements = t.elements;
+    plan->shape = resolve_ragged_shape(sh, plan->total_units, *dev);
+    if (plan->count > 0) {
+        const size_t desc_bytes = sizeof(RaggedDesc) * t.desc.size();
+        const size_t bytes = desc_bytes + sizeof(int64_t) * t.ubeg.size();
+        if (hipMalloc((void **)&plan->dev_buf, bytes) != hipSuccess)
+            return set_error(SINCOS_ENOMEM, "plan_create: cannot allocate the device table");
+        std::vector<char> host(bytes);
+        std::memcpy(host.data(), t.desc.data(), desc_bytes);
+        std::memcpy(host.data() + desc_bytes, t.ubeg.data(), sizeof(int64_t) * t.ubeg.size());
+        hipError_t e = hipMemcpy(plan->dev_buf, host.data(), bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(plan->dev_buf);
+            return hip_error(e, "plan_create: table copy");
+        }
+        plan->d_desc = reinterpret_cast<RaggedDesc *>(plan->dev_buf);
+        plan->d_ubeg = reinterpret_cast<int64_t *>(plan->dev_buf + desc_bytes);
+    }
+    *out_plan = plan.release();
+    return SINCOS_OK;
+}
+
+extern "C" int sincos_ragged_plan_launch(const sincos_ragged_plan_t *plan, void *stream)
+{
+    clear_error();
+    if (!plan)
+        return set_error(SINCOS_EINVAL, "plan_launch: null plan");
+    if (plan->count == 0)
+        return SINCOS_OK;
+    hipError_t e = launch_ragged(plan->d_desc, plan->d_ubeg, plan->count, plan->total_units,
+                                 plan->arith, plan->method, plan->shape, (hipStream_t)stream);
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "plan_launch: kernel launch");
+}
+
+extern "C" int sincos_ragged_plan_graph_launch(sincos_ragged_plan_t *plan, void *stream)
+{
+    clear_error();
+    if (!plan)
+        return set_error(SINCOS_EINVAL, "plan_graph_launch: null plan");
+    if (plan->count == 0)
+        return SINCOS_OK;
+    hipError_t e;
+    if (!plan->exec) {
+        if (!plan->capture_stream &&
+            (e = hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking)) != hipSuccess)
+            return hip_error(e, "plan_graph_launch: capture stream");
+        if ((e = hipStreamBeginCapture(plan->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_error(e, "plan_graph_launch: begin capture");
+        hipError_t le = launch_ragged(plan->d_desc, plan->d_ubeg, plan->count, plan->total_units,
+                                      plan->arith, plan->method, plan->shape, plan->capture_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(plan->capture_stream, &g);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return hip_error(le != hipSuccess ? le : e, "plan_graph_launch: capture");
+        }
+        plan->graph = g;
+        if ((e = hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+            plan->exec = nullptr;
+            return hip_error(e, "plan_graph_launch: instantiate");
+        }
+    }
+    e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "plan_graph_launch: graph launch");
+}
+
+extern "C" int sincos_ragged_plan_info(const sincos_ragged_plan_t *plan, int32_t *block,
+                                       int32_t *unroll, int32_t *grid, int64_t *units,
+                                       int64_t *elements)
+{
+    clear_error();
+    if (!plan)
+        return set_error(SINCOS_EINVAL, "plan_info: null plan");
+    if (block)
+        *block = plan->shape.block;
+    if (unroll)
+        *unroll = plan->shape.unroll;
+    if (grid)
+        *grid = plan->shape.grid;
+    if (units)
+        *units = plan->total_units;
+    if (elements)
+        *elements = plan->elements;
+    return SINCOS_OK;
+}
+
+extern "C" int sincos_ragged_plan_destroy(sincos_ragged_plan_t *plan)
+{
+    clear_error();
+    if (!plan)
+        return SINCOS_OK;
+    if (plan->exec)
+        (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph)
+        (void)hipGraphDestroy(plan->graph);
+    if (plan->capture_stream)
+        (void)hipStreamDestroy(plan->capture_stream);
+    if (plan->dev_buf)
+        (void)hipFree(plan->dev_buf);
+    delete plan;
+    return SINCOS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoints
+
+extern "C" int sincos_f32_backward(const float *s, const float *c, const float *gs,
+                                   const float *gc, float *gx, int64_t n, void *stream)
+{
+    clear_error();
+    if (n < 0)
+        return set_error(SINCOS_EINVAL, "sincos_f32_backward: n < 0");
+    if (n == 0)
+        return SINCOS_OK;
+    if (!s || !c || !gx)
+        return set_error(SINCOS_EINVAL, "sincos_f32_backward: null s, c or gx with n > 0");
+    if (!aligned4(s) || !aligned4(c) || !aligned4(gx) || (gs && !aligned4(gs)) ||
+        (gc && !aligned4(gc)))
+        return set_error(SINCOS_EINVAL, "sincos_f32_backward: pointers must be 4-byte aligned");
+    if (ranges_overlap(gx, n, s, n) || ranges_overlap(gx, n, c, n))
+        return set_error(SINCOS_EOVERLAP, "sincos_f32_backward: gx overlaps s or c");
+    if (gs && gs != gx && ranges_overlap(gx, n, gs, n))
+        return set_error(SINCOS_EOVERLAP, "sincos_f32_backward: gx partially overlaps gs");
+    if (gc && gc != gx && ranges_overlap(gx, n, gc, n))
+        return set_error(SINCOS_EOVERLAP, "sincos_f32_backward: gx partially overlaps gc");
+    const DeviceInfo *dev;
+    int rc;
+    if ((rc = current_device(&dev)) != SINCOS_OK)
+        return rc;
+    hipError_t e = launch_backward(s, c, gs, gc, gx, n, (hipStream_t)stream);
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "sincos_f32_backward: kernel launch");
+}
+
+static int check_params(const float *A, const float *w, const float *phi, int32_t K,
+                        const char *who)
+{
+    if (K < 0)
+        return set_error(SINCOS_EINVAL, std::string(who) + ": K < 0");
+    if (K > 0 && (!A || !w || !phi))
+        return set_error(SINCOS_EINVAL, std::string(who) + ": null parameter array with K > 0");
+    if (K > (1 << 20))
+        return set_error(SINCOS_EINVAL, std::string(who) + ": K too large");
+    return SINCOS_OK;
+}
+
+extern "C" int sinusoid_f32_forward(const float *t, int64_t N, const float *A, const float *w,
+                                    const float *phi, int32_t K, float *y, void *stream)
+{
+    clear_error();
+    if (N < 0)
+        return set_error(SINCOS_EINVAL, "sinusoid_f32_forward: N < 0");
+    int rc = check_params(A, w, phi, K, "sinusoid_f32_forward");
+    if (rc != SINCOS_OK)
+        return rc;
+    if (N == 0)
+        return SINCOS_OK;
+    if (!t || !y)
+        return set_error(SINCOS_EINVAL, "sinusoid_f32_forward: null t or y with N > 0");
+    if (ranges_overlap(t, N, y, N) && t != y)
+        return set_error(SINCOS_EOVERLAP, "sinusoid_f32_forward: t partially overlaps y");
+    const DeviceInfo *dev;
+    if ((rc = current_device(&dev)) != SINCOS_OK)
+        return rc;
+    hipError_t e = launch_sinusoid_forward(t, N, A, w, phi, K, y, (hipStream_t)stream);
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "sinusoid_f32_forward: kernel launch");
+}
+
+extern "C" int64_t sinusoid_f32_backward_workspace_bytes(int64_t N, int32_t K)
+{
+    if (N < 0 || K < 0)
+        return -1;
+    return sinusoid_chunks(N) * 3 * sinusoid_kgroups(K) * 64 * (int64_t)sizeof(float);
+}
+
+extern "C" int sinusoid_f32_backward(const float *t, const float *g, int64_t N, const float *A,
+                                     const float *w, const float *phi, int32_t K, float *gA,
+                                     float *gw, float *gphi, void *workspace,
+                                     int64_t workspace_bytes, void *stream)
+{
+    clear_error();
+    if (N < 0)
+        return set_error(SINCOS_EINVAL, "sinusoid_f32_backward: N < 0");
+    int rc = check_params(A, w, phi, K, "sinusoid_f32_backward");
+    if (rc != SINCOS_OK)
+        return rc;
+    if (K == 0)
+        return SINCOS_OK;
+    if (!gA || !gw || !gphi)
+        return set_error(SINCOS_EINVAL, "sinusoid_f32_backward: null gradient output");
+    if (N > 0 && (!t || !g))
+        return set_error(SINCOS_EINVAL, "sinusoid_f32_backward: null t or g with N > 0");
+    const int64_t need = sinusoid_f32_backward_workspace_bytes(N, K);
+    if (N > 0 && (!workspace || workspace_bytes < need))
+        return set_error(SINCOS_EINVAL, "sinusoid_f32_backward: workspace needs " +
+                                            std::to_string(need) + " bytes");
+    const DeviceInfo *dev;
+    if ((rc = current_device(&dev)) != SINCOS_OK)
+        return rc;
+    hipError_t e = launch_sinusoid_backward(t, g, N, A, w, phi, K, gA, gw, gphi,
+                                            static_cast<float *>(workspace), (hipStream_t)stream);
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "sinusoid_f32_backward: kernel launch");
+}
+
+// ---------------------------------------------------------------------------
+
+extern "C" const char *sincos_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *sincos_version(void) { return "mi355-sincos 0.1 (gfx950)"; }

@@ -1,0 +1,71 @@
+// internal.hpp -- declarations shared by the library's translation units
+// (kernel launchers, the C ABI and the request server).  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+namespace mi355 {
+
+// One ragged segment as the kernel reads it (device memory, 48 bytes).
+struct RaggedDesc {
+    const float *x;
+    float *s;
+    float *c;
+    int64_t n;     // elements in the segment
+    int64_t n4;    // float4 in the body (vector segments); 0 for scalar ones
+    int32_t head;  // scalar elements before the float4 body (vector segments)
+    int32_t vec;   // 1: float4 body + head/tail scalars; 0: all scalar
+};
+static_assert(sizeof(RaggedDesc) == 48, "descriptor layout");
+
+struct LaunchShape {
+    int block = 256;
+    int unroll = 4;
+    int grid = 0;
+};
+
+// Device facts the launchers need (cached per device).
+struct DeviceInfo {
+    int device = -1;
+    int cus = 0;
+    int arch_ok = 0;
+    std::string arch;
+};
+const DeviceInfo &device_info(int device);
+
+// ---- launchers (kernels.hip); each returns the hipError_t of the launch ----
+hipError_t launch_sincos(const float *x, float *s, float *c, int64_t n, int arith, int method,
+                         const LaunchShape &shape, hipStream_t stream);
+hipError_t launch_copy_ceiling(const float *x, float *s, float *c, int64_t n,
+                               const LaunchShape &shape, hipStream_t stream);
+hipError_t launch_ragged(const RaggedDesc *desc, const int64_t *ubeg, int32_t count,
+                         int64_t total_units, int arith, int method, const LaunchShape &shape,
+                         hipStream_t stream);
+hipError_t launch_backward(const float *s, const float *c, const float *gs, const float *gc,
+                           float *gx, int64_t n, hipStream_t stream);
+hipError_t launch_sinusoid_forward(const float *t, int64_t N, const float *A, const float *w,
+                                   const float *phi, int32_t K, float *y, hipStream_t stream);
+int64_t sinusoid_chunks(int64_t N);
+int64_t sinusoid_kgroups(int32_t K);
+hipError_t launch_sinusoid_backward(const float *t, const float *g, int64_t N, const float *A,
+                                    const float *w, const float *phi, int32_t K, float *gA,
+                                    float *gw, float *gphi, float *partial, hipStream_t stream);
+
+// Units of work of one ragged segment for a launch shape (host and plan use).
+int64_t ragged_units(const RaggedDesc &d, const LaunchShape &shape);
+// Build a descriptor for (x, s, c, n); n > 0.
+RaggedDesc make_desc(const float *x, float *s, float *c, int64_t n);
+
+// Default launch shapes (resolved against the device).
+LaunchShape resolve_plain_shape(const LaunchShape &req, int64_t n, const DeviceInfo &dev);
+LaunchShape resolve_ragged_shape(const LaunchShape &req, int64_t total_units,
+                                 const DeviceInfo &dev);
+
+// Thread-local error reporting used by every C entry point.
+int set_error(int status, const std::string &msg);
+void clear_error();
+
+}  // namespace mi355

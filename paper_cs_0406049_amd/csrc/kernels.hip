@@ -1,0 +1,604 @@
+// kernels.hip -- gfx950 kernels of the sine-cosine library and their launchers.
+//
+// Every kernel is elementwise over binary32 VALU arithmetic (sincos_core.hpp);
+// the plain and ragged forms are bound by HBM traffic (4 bytes read, 8 bytes
+// written per element), so the kernels are written for streaming: float4
+// (16-byte) loads and stores per lane, several float4 in flight per lane,
+// non-temporal hints (the data is touched once and is far larger than the
+// caches), and 64-bit indexing throughout.
+#include "internal.hpp"
+#include "sincos_core.hpp"
+
+#include <algorithm>
+
+namespace mi355 {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Small device helpers.
+
+template <Arith A, Method M>
+__device__ __forceinline__ void pair4(const f4 v, f4 &so, f4 &co)
+{
+    float s0, s1, s2, s3, c0, c1, c2, c3;
+    sincos_pair<A, M>(v.x, s0, c0);
+    sincos_pair<A, M>(v.y, s1, c1);
+    sincos_pair<A, M>(v.z, s2, c2);
+    sincos_pair<A, M>(v.w, s3, c3);
+    so = f4{s0, s1, s2, s3};
+    co = f4{c0, c1, c2, c3};
+}
+
+template <Arith A, Method M>
+__device__ __forceinline__ void pair1_store(const float *x, float *s, float *c, int64_t i)
+{
+    float so, co;
+    sincos_pair<A, M>(x[i], so, co);
+    s[i] = so;
+    c[i] = co;
+}
+
+// One block's share of a float4 stream: U float4 per lane, lanes strided by
+// the block size so that each of the U loads is one coalesced row.
+template <Arith A, Method M, int U>
+__device__ __forceinline__ void stream_vec_tile(const f4 *xv, f4 *sv, f4 *cv, int64_t base,
+                                                int64_t n4, int64_t bd)
+{
+    f4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t j = base + u * bd;
+        v[u] = j < n4 ? __builtin_nontemporal_load(xv + j) : f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t j = base + u * bd;
+        if (j < n4) {
+            f4 so, co;
+            pair4<A, M>(v[u], so, co);
+            __builtin_nontemporal_store(so, sv + j);
+            __builtin_nontemporal_store(co, cv + j);
+        }
+    }
+}
+
+// Scalar version: U*4 elements per lane per trip.
+template <Arith A, Method M, int U>
+__device__ __forceinline__ void stream_scalar_tile(const float *x, float *s, float *c,
+                                                   int64_t base, int64_t n, int64_t bd)
+{
+    constexpr int R = 4 * U;
+    float v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t j = base + r * bd;
+        v[r] = j < n ? __builtin_nontemporal_load(x + j) : 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t j = base + r * bd;
+        if (j < n) {
+            float so, co;
+            sincos_pair<A, M>(v[r], so, co);
+            __builtin_nontemporal_store(so, s + j);
+            __builtin_nontemporal_store(co, c + j);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K1: plain form.  x, s, c share their offset modulo 16 bytes; `head` scalar
+// elements precede the 16-byte aligned float4 body of n4 vectors and `tail`
+// scalar elements follow it.  Block 0 also does the <= 6 scalar elements.
+
+template <Arith A, Method M, int U>
+__global__ void __launch_bounds__(1024) k_sincos_vec(const float *x, float *s, float *c,
+                                                     int64_t n4, int head, int tail)
+{
+    if (blockIdx.x == 0) {
+        const int t = threadIdx.x;
+        if (t < head) {
+            pair1_store<A, M>(x, s, c, t);
+        } else if (t >= 4 && t < 4 + tail) {
+            pair1_store<A, M>(x, s, c, head + 4 * n4 + (t - 4));
+        }
+    }
+    const f4 *xv = reinterpret_cast<const f4 *>(x + head);
+    f4 *sv = reinterpret_cast<f4 *>(s + head);
+    f4 *cv = reinterpret_cast<f4 *>(c + head);
+    const int64_t bd = blockDim.x;
+    const int64_t stride = (int64_t)gridDim.x * bd * U;
+    for (int64_t base = (int64_t)blockIdx.x * bd * U + threadIdx.x; base < n4; base += stride)
+        stream_vec_tile<A, M, U>(xv, sv, cv, base, n4, bd);
+}
+
+// x, s, c with different offsets modulo 16 bytes: scalar stream.
+template <Arith A, Method M, int U>
+__global__ void __launch_bounds__(1024) k_sincos_scalar(const float *x, float *s, float *c,
+                                                        int64_t n)
+{
+    const int64_t bd = blockDim.x;
+    const int64_t stride = (int64_t)gridDim.x * bd * U * 4;
+    for (int64_t base = (int64_t)blockIdx.x * bd * U * 4 + threadIdx.x; base < n; base += stride)
+        stream_scalar_tile<A, M, U>(x, s, c, base, n, bd);
+}
+
+// Bandwidth ceiling: the plain kernel's traffic with no arithmetic.
+template <int U>
+__global__ void __launch_bounds__(1024) k_copy_1r2w(const f4 *x, f4 *s, f4 *c, int64_t n4)
+{
+    const int64_t bd = blockDim.x;
+    const int64_t stride = (int64_t)gridDim.x * bd * U;
+    for (int64_t base = (int64_t)blockIdx.x * bd * U + threadIdx.x; base < n4; base += stride) {
+        f4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = base + u * bd;
+            v[u] = j < n4 ? __builtin_nontemporal_load(x + j) : f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = base + u * bd;
+            if (j < n4) {
+                __builtin_nontemporal_store(v[u], s + j);
+                __builtin_nontemporal_store(v[u], c + j);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K2: ragged form, one persistent launch over many segments.
+// Work is cut into units: a vector segment's unit is block*U float4 of its
+// body (unit 0 also does its <= 6 head/tail scalars), a scalar segment's unit
+// is block*U*4 elements.  ubeg[j] is the first unit of segment j (ubeg[count]
+// = total).  Block b owns the contiguous units [b*per, (b+1)*per): it finds
+// its first segment by binary search and then walks forward, so segment
+// lookups cost O(1) per unit.  Segment fields are wave-uniform (scalar loads).
+
+template <Arith A, Method M, int U>
+__global__ void __launch_bounds__(1024) k_ragged(const RaggedDesc *__restrict__ desc,
+                                                 const int64_t *__restrict__ ubeg, int32_t count,
+                                                 int64_t total_units, int64_t per_block)
+{
+    const int64_t u0 = (int64_t)blockIdx.x * per_block;
+    const int64_t u1 = min(u0 + per_block, total_units);
+    if (u0 >= u1)
+        return;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {  // largest j with ubeg[j] <= u0
+        const int mid = (lo + hi + 1) >> 1;
+        if (ubeg[mid] <= u0)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    int seg = lo;
+    const int64_t bd = blockDim.x;
+    for (int64_t unit = u0; unit < u1; ++unit) {
+        while (ubeg[seg + 1] <= unit)
+            ++seg;
+        const RaggedDesc d = desc[seg];
+        const int64_t local = unit - ubeg[seg];
+        if (d.vec) {
+            if (local == 0) {
+                const int t = threadIdx.x;
+                const int tail = (int)(d.n - d.head - 4 * d.n4);
+                if (t < d.head)
+                    pair1_store<A, M>(d.x, d.s, d.c, t);
+                else if (t >= 4 && t < 4 + tail)
+                    pair1_store<A, M>(d.x, d.s, d.c, d.head + 4 * d.n4 + (t - 4));
+            }
+            const f4 *xv = reinterpret_cast<const f4 *>(d.x + d.head);
+            f4 *sv = reinterpret_cast<f4 *>(d.s + d.head);
+            f4 *cv = reinterpret_cast<f4 *>(d.c + d.head);
+            stream_vec_tile<A, M, U>(xv, sv, cv, local * bd * U + threadIdx.x, d.n4, bd);
+        } else {
+            stream_scalar_tile<A, M, U>(d.x, d.s, d.c, local * bd * U * 4 + threadIdx.x, d.n, bd);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K3: adjoint of the pair, gx = gs*c - gc*s (absent gradient = 0).
+
+template <bool GS, bool GC>
+__device__ __forceinline__ float adjoint1(float s, float c, float gs, float gc)
+{
+    const float a = GS ? gs * c : 0.0f;
+    const float b = GC ? gc * s : 0.0f;
+    return a - b;
+}
+
+template <bool GS, bool GC>
+__global__ void __launch_bounds__(256) k_backward_vec(const f4 *s, const f4 *c, const f4 *gs,
+                                                      const f4 *gc, f4 *gx, int64_t n4)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        const f4 sv = __builtin_nontemporal_load(s + i);
+        const f4 cv = __builtin_nontemporal_load(c + i);
+        f4 a = f4{0.f, 0.f, 0.f, 0.f}, b = f4{0.f, 0.f, 0.f, 0.f};
+        if (GS)
+            a = __builtin_nontemporal_load(gs + i);
+        if (GC)
+            b = __builtin_nontemporal_load(gc + i);
+        f4 r;
+        r.x = adjoint1<GS, GC>(sv.x, cv.x, a.x, b.x);
+        r.y = adjoint1<GS, GC>(sv.y, cv.y, a.y, b.y);
+        r.z = adjoint1<GS, GC>(sv.z, cv.z, a.z, b.z);
+        r.w = adjoint1<GS, GC>(sv.w, cv.w, a.w, b.w);
+        __builtin_nontemporal_store(r, gx + i);
+    }
+}
+
+template <bool GS, bool GC>
+__global__ void __launch_bounds__(256) k_backward_scalar(const float *s, const float *c,
+                                                         const float *gs, const float *gc,
+                                                         float *gx, int64_t lo, int64_t hi)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += stride)
+        gx[i] = adjoint1<GS, GC>(s[i], c[i], GS ? gs[i] : 0.f, GC ? gc[i] : 0.f);
+}
+
+// ---------------------------------------------------------------------------
+// K4: sinusoid model forward, y_i = sum_k A_k sin(w_k t_i + phi_k).
+// Lane <-> sample: each lane keeps IPT samples and walks k in order, so the
+// sum order is k = 0..K-1 exactly; A_k, w_k, phi_k are wave-uniform (scalar
+// loads).  Only the sine of each pair is used; the cosine-only operations
+// are dropped by the compiler.
+
+constexpr int kFwdIPT = 4;
+
+__global__ void __launch_bounds__(256) k_sinusoid_fwd(const float *t, int64_t N,
+                                                      const float *__restrict__ A,
+                                                      const float *__restrict__ w,
+                                                      const float *__restrict__ phi, int32_t K,
+                                                      float *y)
+{
+    const int64_t bd = blockDim.x;
+    const int64_t stride = (int64_t)gridDim.x * bd * kFwdIPT;
+    for (int64_t base = (int64_t)blockIdx.x * bd * kFwdIPT + threadIdx.x; base < N;
+         base += stride) {
+        float ti[kFwdIPT], acc[kFwdIPT];
+#pragma unroll
+        for (int r = 0; r < kFwdIPT; ++r) {
+            const int64_t i = base + r * bd;
+            ti[r] = i < N ? t[i] : 0.f;
+            acc[r] = 0.0f;
+        }
+        for (int32_t k = 0; k < K; ++k) {
+            const float wk = w[k], pk = phi[k], ak = A[k];
+#pragma unroll
+            for (int r = 0; r < kFwdIPT; ++r) {
+                float sv, cv;
+                sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(wk, ti[r], pk), sv, cv);
+                acc[r] = __builtin_fmaf(ak, sv, acc[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kFwdIPT; ++r) {
+            const int64_t i = base + r * bd;
+            if (i < N)
+                y[i] = acc[r];
+        }
+    }
+}
+
+// K5: sinusoid adjoint.  Lane <-> frequency k (a wave covers 64 of them),
+// wave <-> chunk of consecutive samples: t_i and g_i are wave-uniform (scalar
+// loads), so each lane accumulates its own three sums with no cross-lane
+// traffic.  Partial sums go to partial[(j * Kpad + k) * nchunks + chunk]
+// (j = 0: A, 1: phi, 2: w); k_sinusoid_reduce adds each row in a fixed tree
+// order (deterministic) and applies A_k.
+
+constexpr int64_t kAdjChunk = 1024;  // samples per wave
+constexpr int kAdjWaves = 4;         // waves per block (one chunk each)
+
+__global__ void __launch_bounds__(256) k_sinusoid_adj(const float *__restrict__ t,
+                                                      const float *__restrict__ g, int64_t N,
+                                                      const float *__restrict__ w,
+                                                      const float *__restrict__ phi, int32_t K,
+                                                      int64_t nchunks, float *partial)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t chunk = (int64_t)blockIdx.x * kAdjWaves + wave;
+    const int kg = blockIdx.y;
+    const int32_t Kpad = (int32_t)gridDim.y * 64;
+    const int32_t k = kg * 64 + lane;
+    if (chunk >= nchunks)
+        return;
+    const bool active = k < K;
+    const float wk = active ? w[k] : 0.f;
+    const float pk = active ? phi[k] : 0.f;
+    float sa = 0.f, sp = 0.f, sw = 0.f;
+    const int64_t i0 = chunk * kAdjChunk;
+    const int64_t i1 = min(i0 + kAdjChunk, N);
+#pragma unroll 8
+    for (int64_t i = i0; i < i1; ++i) {
+        const float ti = t[i], gi = g[i];
+        float sv, cv;
+        sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(wk, ti, pk), sv, cv);
+        sa = __builtin_fmaf(gi, sv, sa);
+        sp = __builtin_fmaf(gi, cv, sp);
+        sw = __builtin_fmaf(gi * ti, cv, sw);
+    }
+    partial[((int64_t)0 * Kpad + k) * nchunks + chunk] = sa;
+    partial[((int64_t)1 * Kpad + k) * nchunks + chunk] = sp;
+    partial[((int64_t)2 * Kpad + k) * nchunks + chunk] = sw;
+}
+
+// One block per output (j, k): each thread sums a strided share of the row,
+// then a fixed-shape tree in LDS.
+__global__ void __launch_bounds__(256) k_sinusoid_reduce(const float *partial, int64_t nchunks,
+                                                         int32_t Kpad, int32_t K, const float *A,
+                                                         float *gA, float *gw, float *gphi)
+{
+    const int32_t k = blockIdx.x;
+    const int j = blockIdx.y;  // 0: A, 1: phi, 2: w
+    __shared__ float red[256];
+    const float *row = partial + ((int64_t)j * Kpad + k) * nchunks;
+    float acc = 0.f;
+    for (int64_t ch = threadIdx.x; ch < nchunks; ch += blockDim.x)
+        acc += row[ch];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && k < K) {
+        const float v = red[0];
+        if (j == 0)
+            gA[k] = v;
+        else if (j == 1)
+            gphi[k] = A[k] * v;
+        else
+            gw[k] = A[k] * v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+namespace {
+
+template <Arith A, Method M>
+hipError_t launch_plain_am(const float *x, float *s, float *c, int64_t n,
+                           const LaunchShape &sh, hipStream_t st)
+{
+    const uintptr_t ax = reinterpret_cast<uintptr_t>(x), as = reinterpret_cast<uintptr_t>(s),
+                    ac = reinterpret_cast<uintptr_t>(c);
+    const bool same_phase = (ax & 15) == (as & 15) && (ax & 15) == (ac & 15);
+    const int64_t head = same_phase ? (int64_t)(((16 - (ax & 15)) & 15) >> 2) : 0;
+    if (!same_phase || n < head + 4) {
+        const int64_t per_block = (int64_t)sh.block * sh.unroll * 4;
+        int64_t grid = (n + per_block - 1) / per_block;
+        if (sh.grid > 0)
+            grid = std::min<int64_t>(grid, sh.grid);
+        grid = std::max<int64_t>(grid, 1);
+#define MI355_SCALAR(UU)                                                                       \
+    hipLaunchKernelGGL((k_sincos_scalar<A, M, UU>), dim3((unsigned)grid), dim3(sh.block), 0, st, \
+                       x, s, c, n)
+        switch (sh.unroll) {
+        case 1: MI355_SCALAR(1); break;
+        case 2: MI355_SCALAR(2); break;
+        case 8: MI355_SCALAR(8); break;
+        default: MI355_SCALAR(4); break;
+        }
+#undef MI355_SCALAR
+        return hipGetLastError();
+    }
+    const int64_t n4 = (n - head) / 4;
+    const int tail = (int)(n - head - 4 * n4);
+    const int64_t per_block = (int64_t)sh.block * sh.unroll;
+    int64_t grid = (n4 + per_block - 1) / per_block;
+    if (sh.grid > 0)
+        grid = std::min<int64_t>(grid, sh.grid);
+    grid = std::max<int64_t>(grid, 1);
+#define MI355_VEC(UU)                                                                        \
+    hipLaunchKernelGGL((k_sincos_vec<A, M, UU>), dim3((unsigned)grid), dim3(sh.block), 0, st, \
+                       x, s, c, n4, (int)head, tail)
+    switch (sh.unroll) {
+    case 1: MI355_VEC(1); break;
+    case 2: MI355_VEC(2); break;
+    case 8: MI355_VEC(8); break;
+    default: MI355_VEC(4); break;
+    }
+#undef MI355_VEC
+    return hipGetLastError();
+}
+
+template <Arith A, Method M>
+hipError_t launch_ragged_am(const RaggedDesc *desc, const int64_t *ubeg, int32_t count,
+                            int64_t total_units, const LaunchShape &sh, hipStream_t st)
+{
+    const int64_t grid = std::max(1, sh.grid);
+    const int64_t per = (total_units + grid - 1) / grid;
+#define MI355_RAGGED(UU)                                                                     \
+    hipLaunchKernelGGL((k_ragged<A, M, UU>), dim3((unsigned)grid), dim3(sh.block), 0, st, desc, \
+                       ubeg, count, total_units, per)
+    switch (sh.unroll) {
+    case 1: MI355_RAGGED(1); break;
+    case 2: MI355_RAGGED(2); break;
+    case 8: MI355_RAGGED(8); break;
+    default: MI355_RAGGED(4); break;
+    }
+#undef MI355_RAGGED
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sincos(const float *x, float *s, float *c, int64_t n, int arith, int method,
+                         const LaunchShape &sh, hipStream_t st)
+{
+    const bool m2 = method == (int)Method::Arctan;
+    switch (arith) {
+    case (int)Arith::Split:
+        return m2 ? launch_plain_am<Arith::Split, Method::Arctan>(x, s, c, n, sh, st)
+                  : launch_plain_am<Arith::Split, Method::Normalized>(x, s, c, n, sh, st);
+    case (int)Arith::Contract:
+        return m2 ? launch_plain_am<Arith::Contract, Method::Arctan>(x, s, c, n, sh, st)
+                  : launch_plain_am<Arith::Contract, Method::Normalized>(x, s, c, n, sh, st);
+    default:
+        return m2 ? launch_plain_am<Arith::Fused, Method::Arctan>(x, s, c, n, sh, st)
+                  : launch_plain_am<Arith::Fused, Method::Normalized>(x, s, c, n, sh, st);
+    }
+}
+
+hipError_t launch_copy_ceiling(const float *x, float *s, float *c, int64_t n,
+                               const LaunchShape &sh, hipStream_t st)
+{
+    const int64_t n4 = n / 4;  // caller guarantees 16-byte alignment and n % 4 == 0
+    const int64_t per_block = (int64_t)sh.block * sh.unroll;
+    int64_t grid = (n4 + per_block - 1) / per_block;
+    if (sh.grid > 0)
+        grid = std::min<int64_t>(grid, sh.grid);
+    grid = std::max<int64_t>(grid, 1);
+    const f4 *xv = reinterpret_cast<const f4 *>(x);
+    f4 *sv = reinterpret_cast<f4 *>(s);
+    f4 *cv = reinterpret_cast<f4 *>(c);
+#define MI355_COPY(UU)                                                                     \
+    hipLaunchKernelGGL((k_copy_1r2w<UU>), dim3((unsigned)grid), dim3(sh.block), 0, st, xv, sv, \
+                       cv, n4)
+    switch (sh.unroll) {
+    case 1: MI355_COPY(1); break;
+    case 2: MI355_COPY(2); break;
+    case 8: MI355_COPY(8); break;
+    default: MI355_COPY(4); break;
+    }
+#undef MI355_COPY
+    return hipGetLastError();
+}
+
+hipError_t launch_ragged(const RaggedDesc *desc, const int64_t *ubeg, int32_t count,
+                         int64_t total_units, int arith, int method, const LaunchShape &sh,
+                         hipStream_t st)
+{
+    const bool m2 = method == (int)Method::Arctan;
+    switch (arith) {
+    case (int)Arith::Split:
+        return m2 ? launch_ragged_am<Arith::Split, Method::Arctan>(desc, ubeg, count, total_units, sh, st)
+                  : launch_ragged_am<Arith::Split, Method::Normalized>(desc, ubeg, count, total_units, sh, st);
+    case (int)Arith::Contract:
+        return m2 ? launch_ragged_am<Arith::Contract, Method::Arctan>(desc, ubeg, count, total_units, sh, st)
+                  : launch_ragged_am<Arith::Contract, Method::Normalized>(desc, ubeg, count, total_units, sh, st);
+    default:
+        return m2 ? launch_ragged_am<Arith::Fused, Method::Arctan>(desc, ubeg, count, total_units, sh, st)
+                  : launch_ragged_am<Arith::Fused, Method::Normalized>(desc, ubeg, count, total_units, sh, st);
+    }
+}
+
+int64_t ragged_units(const RaggedDesc &d, const LaunchShape &sh)
+{
+    if (d.vec) {
+        const int64_t per = (int64_t)sh.block * sh.unroll;
+        return std::max<int64_t>(1, (d.n4 + per - 1) / per);
+    }
+    const int64_t per = (int64_t)sh.block * sh.unroll * 4;
+    return (d.n + per - 1) / per;
+}
+
+RaggedDesc make_desc(const float *x, float *s, float *c, int64_t n)
+{
+    RaggedDesc d{x, s, c, n, 0, 0, 0};
+    const uintptr_t ax = reinterpret_cast<uintptr_t>(x), as = reinterpret_cast<uintptr_t>(s),
+                    ac = reinterpret_cast<uintptr_t>(c);
+    const bool same_phase = (ax & 15) == (as & 15) && (ax & 15) == (ac & 15);
+    const int64_t head = same_phase ? (int64_t)(((16 - (ax & 15)) & 15) >> 2) : 0;
+    if (same_phase && n >= head + 16) {
+        d.vec = 1;
+        d.head = (int32_t)head;
+        d.n4 = (n - head) / 4;
+    }
+    return d;
+}
+
+hipError_t launch_backward(const float *s, const float *c, const float *gs, const float *gc,
+                           float *gx, int64_t n, hipStream_t st)
+{
+    const uintptr_t phase = reinterpret_cast<uintptr_t>(s) & 15;
+    bool vec = (reinterpret_cast<uintptr_t>(c) & 15) == phase &&
+               (reinterpret_cast<uintptr_t>(gx) & 15) == phase &&
+               (!gs || (reinterpret_cast<uintptr_t>(gs) & 15) == phase) &&
+               (!gc || (reinterpret_cast<uintptr_t>(gc) & 15) == phase);
+    const int64_t head = vec ? (int64_t)(((16 - phase) & 15) >> 2) : 0;
+    if (n < head + 4)
+        vec = false;
+    const int64_t n4 = vec ? (n - head) / 4 : 0;
+    const int64_t body_end = vec ? head + 4 * n4 : 0;
+    auto scalar = [&](int64_t lo, int64_t hi) {
+        if (hi <= lo)
+            return;
+        const int64_t grid = std::min<int64_t>((hi - lo + 255) / 256, 8192);
+#define MI355_BWD_S(GS, GC)                                                                       \
+    hipLaunchKernelGGL((k_backward_scalar<GS, GC>), dim3((unsigned)grid), dim3(256), 0, st, s, c, \
+                       gs, gc, gx, lo, hi)
+        if (gs && gc) MI355_BWD_S(true, true);
+        else if (gs) MI355_BWD_S(true, false);
+        else if (gc) MI355_BWD_S(false, true);
+        else MI355_BWD_S(false, false);
+#undef MI355_BWD_S
+    };
+    if (!vec) {
+        scalar(0, n);
+        return hipGetLastError();
+    }
+    scalar(0, head);
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((n4 + 255) / 256, 16384));
+    const f4 *sv = reinterpret_cast<const f4 *>(s + head);
+    const f4 *cv = reinterpret_cast<const f4 *>(c + head);
+    const f4 *gsv = gs ? reinterpret_cast<const f4 *>(gs + head) : nullptr;
+    const f4 *gcv = gc ? reinterpret_cast<const f4 *>(gc + head) : nullptr;
+    f4 *gxv = reinterpret_cast<f4 *>(gx + head);
+#define MI355_BWD_V(GS, GC)                                                                       \
+    hipLaunchKernelGGL((k_backward_vec<GS, GC>), dim3((unsigned)grid), dim3(256), 0, st, sv, cv, \
+                       gsv, gcv, gxv, n4)
+    if (gs && gc) MI355_BWD_V(true, true);
+    else if (gs) MI355_BWD_V(true, false);
+    else if (gc) MI355_BWD_V(false, true);
+    else MI355_BWD_V(false, false);
+#undef MI355_BWD_V
+    scalar(body_end, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sinusoid_forward(const float *t, int64_t N, const float *A, const float *w,
+                                   const float *phi, int32_t K, float *y, hipStream_t st)
+{
+    const int64_t per_block = 256 * kFwdIPT;
+    const int64_t grid = std::max<int64_t>(1, (N + per_block - 1) / per_block);
+    hipLaunchKernelGGL(k_sinusoid_fwd, dim3((unsigned)grid), dim3(256), 0, st, t, N, A, w, phi, K,
+                       y);
+    return hipGetLastError();
+}
+
+int64_t sinusoid_chunks(int64_t N) { return (N + kAdjChunk - 1) / kAdjChunk; }
+int64_t sinusoid_kgroups(int32_t K) { return std::max<int64_t>(1, ((int64_t)K + 63) / 64); }
+
+hipError_t launch_sinusoid_backward(const float *t, const float *g, int64_t N, const float *A,
+                                    const float *w, const float *phi, int32_t K, float *gA,
+                                    float *gw, float *gphi, float *partial, hipStream_t st)
+{
+    const int64_t nchunks = sinusoid_chunks(N);
+    const int64_t kg = sinusoid_kgroups(K);
+    const int32_t Kpad = (int32_t)(kg * 64);
+    if (nchunks > 0) {
+        const int64_t blocks = (nchunks + kAdjWaves - 1) / kAdjWaves;
+        hipLaunchKernelGGL(k_sinusoid_adj, dim3((unsigned)blocks, (unsigned)kg), dim3(64 * kAdjWaves),
+                           0, st, t, g, N, w, phi, K, nchunks, partial);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(k_sinusoid_reduce, dim3((unsigned)Kpad, 3), dim3(256), 0, st, partial,
+                       nchunks, Kpad, K, A, gA, gw, gphi);
+    return hipGetLastError();
+}
+
+}  // namespace mi355

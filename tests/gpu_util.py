@@ -1,0 +1,34 @@
+"""Helpers shared by the GPU tests (comparison, device buffers)."""
+import numpy as np
+
+
+def lib_loaded():
+    """The HIP library, loaded; GPU tests fail (not skip) if it is missing."""
+    from paper_cs_0406049_amd import _capi
+    return _capi.lib()
+
+
+def bits(a):
+    return np.ascontiguousarray(a, np.float32).view(np.uint32)
+
+
+def same_bits_nan_equal(a, b):
+    """Bitwise equality, with any NaN equal to any NaN (payloads may differ)."""
+    a = np.ascontiguousarray(a, np.float32)
+    b = np.ascontiguousarray(b, np.float32)
+    eq = bits(a) == bits(b)
+    both_nan = np.isnan(a) & np.isnan(b)
+    return eq | both_nan
+
+
+def assert_bit_exact(got, want, what="", x=None):
+    ok = same_bits_nan_equal(got, want)
+    if not ok.all():
+        i = int(np.flatnonzero(~ok)[0])
+        extra = "" if x is None else " at x=%r (bits %08x)" % (float(x[i]), int(bits(x[i:i + 1])[0]))
+        raise AssertionError("%s: %d of %d elements differ; first index %d: got %r want %r%s" % (
+            what, int((~ok).sum()), ok.size, i, float(got[i]), float(want[i]), extra))
+
+
+def log(msg):
+    print(msg, flush=True)

@@ -1,0 +1,166 @@
+"""The C-ABI library on a machine with or without a GPU: it loads, exports
+every symbol include/sincos.h declares, and rejects bad arguments on the host
+before any HIP call.  Pointers here are fake addresses that are never
+dereferenced: every case fails validation first (or is a no-op)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_cs_0406049_amd import _capi, build as hipbuild
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sincos.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not hipbuild.is_built():
+        hipbuild.build()
+    return _capi.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"SINCOS_API\s+[\w\s\*]+?\b(\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 16
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_capi._SIGNATURES), "binding and header disagree"
+
+
+def test_only_declared_symbols_are_exported(L):
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", _capi.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = {l.split()[-1] for l in out.splitlines() if " T " in l}
+    assert exported == set(declared_functions()), exported ^ set(declared_functions())
+
+
+def test_version(L):
+    assert "gfx950" in _capi.version()
+
+
+BASE = 1 << 32  # fake, 256-byte aligned addresses
+
+
+def st(rc):
+    return rc, _capi.last_error()
+
+
+def test_plain_validation(L):
+    f = L.sincos_f32
+    assert f(None, None, None, 0, None) == _capi.OK
+    assert st(f(None, None, None, -1, None))[0] == _capi.EINVAL
+    assert st(f(None, BASE, BASE + 4096, 4, None))[0] == _capi.EINVAL
+    assert st(f(BASE + 1, BASE + 4096, BASE + 8192, 4, None))[0] == _capi.EINVAL  # misaligned
+    assert st(f(BASE, BASE + 4096, BASE + 4096, 4, None))[0] == _capi.EOVERLAP    # s == c
+    assert st(f(BASE, BASE + 4096, BASE + 4096 + 8, 4, None))[0] == _capi.EOVERLAP  # s, c overlap
+    assert st(f(BASE, BASE + 8, BASE + 8192, 4, None))[0] == _capi.EOVERLAP       # x partly s
+    assert st(f(BASE + 8, BASE, BASE + 8192, 4, None))[0] == _capi.EOVERLAP
+    assert st(f(BASE, BASE + 8192, BASE + 4, 4, None))[0] == _capi.EOVERLAP       # x partly c
+    ex = L.sincos_f32_ex
+    assert ex(BASE, BASE + 4096, BASE + 8192, 4, 3, 0, None, None) == _capi.EINVAL
+    assert ex(BASE, BASE + 4096, BASE + 8192, 4, 0, 2, None, None) == _capi.EINVAL
+    for bad in ((96, 4, 0), (2048, 4, 0), (256, 3, 0), (256, 4, -1)):
+        rc = ex(BASE, BASE + 4096, BASE + 8192, 4, 0, 0, ctypes.byref(_capi.Launch(*bad, 0)), None)
+        assert rc == _capi.EINVAL, bad
+    assert "launch" in _capi.last_error()
+
+
+def test_in_place_is_accepted_by_validation(L):
+    """x == s (or x == c) passes the argument checks: the call then either
+    runs (GPU present) or reports the missing device, never EOVERLAP."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("covered by the GPU tests")
+    for args in ((BASE, BASE, BASE + 4096), (BASE, BASE + 4096, BASE)):
+        assert L.sincos_f32(*args, 4, None) == _capi.ENODEV
+    assert "device" in _capi.last_error()
+
+
+def seg_tables(segs, lens):
+    S = (_capi.Seg * len(segs))(*[_capi.Seg(*t) for t in segs])
+    N = (ctypes.c_int64 * len(lens))(*lens)
+    return S, N
+
+
+def test_ragged_validation(L):
+    f = L.sincos_f32_ragged
+    S, N = seg_tables([(BASE, BASE + 4096, BASE + 8192)], [4])
+    assert f(S, N, 0, None) == _capi.OK
+    assert f(S, N, -1, None) == _capi.EINVAL
+    assert f(None, N, 1, None) == _capi.EINVAL
+    S, N = seg_tables([(BASE, BASE + 4096, BASE + 8192)], [-3])
+    assert f(S, N, 1, None) == _capi.EINVAL
+    assert "segment 0" in _capi.last_error()
+    # outputs of two segments overlap
+    S, N = seg_tables([(BASE, BASE + 4096, BASE + 8192), (BASE + 100000, BASE + 8192 + 8, BASE + 200000)],
+                      [4, 4])
+    assert f(S, N, 2, None) == _capi.EOVERLAP
+    # input of one segment overlaps an output of another
+    S, N = seg_tables([(BASE, BASE + 4096, BASE + 8192), (BASE + 4096, BASE + 20000, BASE + 30000)],
+                      [4, 4])
+    assert f(S, N, 2, None) == _capi.EOVERLAP
+    # shared inputs, disjoint outputs, and in-place segments pass validation
+    import torch
+    if not torch.cuda.is_available():
+        S, N = seg_tables([(BASE, BASE + 4096, BASE + 8192), (BASE, BASE + 12288, BASE + 16384),
+                           (BASE + 20480, BASE + 20480, BASE + 24576)], [4, 4, 4])
+        assert f(S, N, 3, None) == _capi.ENODEV
+        # zero-length segments are ignored, whatever their pointers
+        S, N = seg_tables([(0, 0, 0), (BASE, BASE + 4096, BASE + 8192)], [0, 4])
+        assert f(S, N, 2, None) == _capi.ENODEV
+
+
+def test_plan_validation(L):
+    h = ctypes.c_void_p()
+    S, N = seg_tables([(BASE, BASE + 4096, BASE + 4096)], [4])
+    assert L.sincos_ragged_plan_create(S, N, 1, 0, 0, None, ctypes.byref(h)) == _capi.EOVERLAP
+    assert not h.value
+    assert L.sincos_ragged_plan_create(S, N, 1, 0, 0, None, None) == _capi.EINVAL
+    assert L.sincos_ragged_plan_launch(None, None) == _capi.EINVAL
+    assert L.sincos_ragged_plan_graph_launch(None, None) == _capi.EINVAL
+    assert L.sincos_ragged_plan_destroy(None) == _capi.OK
+
+
+def test_backward_validation(L):
+    f = L.sincos_f32_backward
+    assert f(None, None, None, None, None, 0, None) == _capi.OK
+    assert f(BASE, BASE + 4096, None, None, BASE + 8192, -1, None) == _capi.EINVAL
+    assert f(BASE, None, None, None, BASE + 8192, 4, None) == _capi.EINVAL
+    assert f(BASE, BASE + 4096, None, None, BASE + 4, 4, None) == _capi.EOVERLAP
+    assert f(BASE, BASE + 4096, BASE + 8192 + 4, None, BASE + 8192, 4, None) == _capi.EOVERLAP
+
+
+def test_sinusoid_validation_and_workspace(L):
+    assert L.sinusoid_f32_forward(None, -1, None, None, None, 0, None, None) == _capi.EINVAL
+    assert L.sinusoid_f32_forward(BASE, 4, None, None, None, 3, BASE + 4096, None) == _capi.EINVAL
+    assert L.sinusoid_f32_forward(None, 0, BASE, BASE, BASE, 3, None, None) == _capi.OK
+    wb = L.sinusoid_f32_backward_workspace_bytes
+    assert wb(-1, 4) == -1
+    assert wb(4_194_304, 64) == 4096 * 3 * 64 * 4
+    assert wb(1025, 65) == 2 * 3 * 128 * 4
+    rc = L.sinusoid_f32_backward(BASE, BASE + 4096, 4096, BASE + 8192, BASE + 8192, BASE + 8192, 64,
+                                 BASE + 9000, BASE + 10000, BASE + 11000, BASE + 20000, 16, None)
+    assert rc == _capi.EINVAL and "workspace" in _capi.last_error()
+
+
+def test_copy_ceiling_validation(L):
+    f = L.sincos_copy_ceiling_f32
+    assert f(BASE, BASE + 4096, BASE + 8192, 6, None, None) == _capi.EINVAL
+    assert f(BASE + 4, BASE + 4096, BASE + 8192, 4, None, None) == _capi.EINVAL
+    assert f(BASE, BASE, BASE + 8192, 4, None, None) == _capi.EOVERLAP
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """No silent fallback: without the built library the binding raises."""
+    monkeypatch.setattr(_capi, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_capi, "_lib", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        _capi.lib()

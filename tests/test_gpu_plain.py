@@ -1,0 +1,192 @@
+"""Plain form on the GPU against the CPU oracle: bit-exact in FUSED and SPLIT
+arithmetic (NaN compared as NaN), within 2^-20 for CONTRACT."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_bit_exact, lib_loaded, log
+
+pytestmark = pytest.mark.gpu
+
+FUSED, SPLIT, CONTRACT = 0, 1, 2
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lib_loaded()
+    return torch
+
+
+def run(torch, x_host, arith=FUSED, method=0, launch=None):
+    from paper_cs_0406049_amd import _capi
+    x = torch.from_numpy(np.ascontiguousarray(x_host, np.float32)).cuda()
+    s = torch.empty_like(x)
+    c = torch.empty_like(x)
+    _capi.sincos_f32_ex(x, s, c, x.numel(), arith, method, launch)
+    torch.cuda.synchronize()
+    return s.cpu().numpy(), c.cpu().numpy()
+
+
+@pytest.mark.parametrize("arith", [FUSED, SPLIT])
+@pytest.mark.parametrize("quarter", [0, 1, 2, 3])
+def test_exhaustive_all_bit_patterns(torch_dev, arith, quarter):
+    """Every one of the 2^32 binary32 inputs, in four quarters per mode."""
+    torch = torch_dev
+    from paper_cs_0406049_amd import _capi
+    chunk = 1 << 26
+    lo_q = quarter << 30
+    threads = oracle.default_threads()
+    xs = torch.empty(chunk, dtype=torch.float32, device="cuda")
+    s = torch.empty_like(xs)
+    c = torch.empty_like(xs)
+    for k in range((1 << 30) // chunk):
+        lo = lo_q + k * chunk
+        xb = np.arange(lo, lo + chunk, dtype=np.uint64).astype(np.uint32).view(np.float32)
+        xs.copy_(torch.from_numpy(xb))
+        _capi.sincos_f32_ex(xs, s, c, chunk, arith, 0)
+        sg, cg = s.cpu().numpy(), c.cpu().numpy()
+        so, co = oracle.sincos(xb, arith, 0, threads=threads)
+        assert_bit_exact(sg, so, "sin bits %08x.." % lo, xb)
+        assert_bit_exact(cg, co, "cos bits %08x.." % lo, xb)
+    log("exhaustive arith=%d quarter=%d: 2^30 inputs bit-exact" % (arith, quarter))
+
+
+@pytest.mark.parametrize("arith", [FUSED, SPLIT])
+@pytest.mark.parametrize("method", [0, 1])
+def test_plain_small_workload(torch_dev, arith, method):
+    from paper_cs_0406049_amd import workloads
+    x = workloads.plain_small()
+    sg, cg = run(torch_dev, x, arith, method)
+    so, co = oracle.sincos(x, arith, method, threads=oracle.default_threads())
+    assert_bit_exact(sg, so, "sin", x)
+    assert_bit_exact(cg, co, "cos", x)
+
+
+@pytest.mark.slow
+def test_plain_roofline_workload_full(torch_dev):
+    """268,435,456 angles in the benchmark's launch configuration (default
+    shape), every element against the oracle, both exact modes."""
+    torch = torch_dev
+    from paper_cs_0406049_amd import _capi, workloads
+    x = workloads.plain_roofline()
+    log("roofline workload generated")
+    xd = torch.from_numpy(x).cuda()
+    s = torch.empty_like(xd)
+    c = torch.empty_like(xd)
+    for arith in (FUSED, SPLIT):
+        if arith == FUSED:
+            _capi.sincos_f32(xd, s, c, xd.numel())
+        else:
+            _capi.sincos_f32_ex(xd, s, c, xd.numel(), arith, 0)
+        torch.cuda.synchronize()
+        so, co = oracle.sincos(x, arith, 0, threads=oracle.default_threads())
+        assert_bit_exact(s.cpu().numpy(), so, "sin", x)
+        assert_bit_exact(c.cpu().numpy(), co, "cos", x)
+        log("roofline workload arith=%d bit-exact" % arith)
+
+
+@pytest.mark.parametrize("launch", [(64, 1, 0), (256, 1, 1), (256, 2, 7), (512, 8, 0),
+                                    (1024, 4, 3), (128, 4, 100)])
+def test_launch_shapes(torch_dev, launch):
+    x = np.random.default_rng(17).uniform(-1e3, 1e3, 1_000_003).astype(np.float32)
+    sg, cg = run(torch_dev, x, FUSED, 0, launch)
+    so, co = oracle.sincos(x, FUSED, 0, threads=oracle.default_threads())
+    assert_bit_exact(sg, so, "sin %r" % (launch,), x)
+    assert_bit_exact(cg, co, "cos %r" % (launch,), x)
+
+
+CANARY = np.uint32(0x7FC0DEAD)
+
+
+@pytest.mark.parametrize("offsets", [(0, 0, 0), (1, 1, 1), (2, 2, 2), (3, 3, 3), (1, 0, 0),
+                                     (0, 2, 3), (3, 1, 2)])
+def test_small_sizes_offsets_and_guard_bands(torch_dev, offsets):
+    """n = 0..70 and n = 4099 at every 16-byte phase (head, float4 body, tail,
+    and the scalar path for mismatched phases); nothing outside [0, n) of
+    each output is written."""
+    torch = torch_dev
+    from paper_cs_0406049_amd import _capi
+    rng = np.random.default_rng(sum(offsets))
+    ox, os_, oc = offsets
+    pad = 64
+    for n in list(range(0, 71)) + [4099, 65536 + 5]:
+        xh = rng.uniform(-50, 50, n).astype(np.float32)
+        X = torch.full((n + 2 * pad,), 0, dtype=torch.float32, device="cuda")
+        S = torch.from_numpy(np.full(n + 2 * pad, CANARY, np.uint32).view(np.float32)).cuda()
+        C = S.clone()
+        X[pad + ox:pad + ox + n] = torch.from_numpy(xh).cuda()
+        xs = X[pad + ox:pad + ox + n]
+        ss = S[pad + os_:pad + os_ + n]
+        cs = C[pad + oc:pad + oc + n]
+        _capi.sincos_f32(xs.data_ptr(), ss.data_ptr(), cs.data_ptr(), n)
+        torch.cuda.synchronize()
+        Sh = S.cpu().numpy().view(np.uint32)
+        Ch = C.cpu().numpy().view(np.uint32)
+        so, co = oracle.sincos(xh, FUSED, 0)
+        assert_bit_exact(Sh[pad + os_:pad + os_ + n].view(np.float32), so, "sin n=%d" % n, xh)
+        assert_bit_exact(Ch[pad + oc:pad + oc + n].view(np.float32), co, "cos n=%d" % n, xh)
+        for arr, o in ((Sh, os_), (Ch, oc)):
+            assert np.all(arr[:pad + o] == CANARY) and np.all(arr[pad + o + n:] == CANARY), n
+
+
+def test_in_place(torch_dev):
+    torch = torch_dev
+    from paper_cs_0406049_amd import _capi
+    xh = np.random.default_rng(5).uniform(-1e4, 1e4, 1 << 20).astype(np.float32)
+    so, co = oracle.sincos(xh, FUSED, 0, threads=oracle.default_threads())
+    x = torch.from_numpy(xh).cuda()
+    c = torch.empty_like(x)
+    _capi.sincos_f32(x, x, c, x.numel())          # s overwrites x
+    torch.cuda.synchronize()
+    assert_bit_exact(x.cpu().numpy(), so, "sin in place")
+    assert_bit_exact(c.cpu().numpy(), co, "cos")
+    x = torch.from_numpy(xh).cuda()
+    s = torch.empty_like(x)
+    _capi.sincos_f32(x, s, x, x.numel())          # c overwrites x
+    torch.cuda.synchronize()
+    assert_bit_exact(s.cpu().numpy(), so, "sin")
+    assert_bit_exact(x.cpu().numpy(), co, "cos in place")
+
+
+def test_special_values(torch_dev):
+    x = np.array([np.inf, -np.inf, np.nan, 0.0, -0.0, 1e-45, -1e-45, 1e-40, 1.17549435e-38,
+                  3.4028235e38, -3.4028235e38, 5.27e7, 6e7, math.pi, -math.pi, math.pi / 2,
+                  math.pi / 4, 0.5 / (1 / (2 * math.pi))], np.float32)
+    for arith in (FUSED, SPLIT):
+        for method in (0, 1):
+            sg, cg = run(torch_dev, x, arith, method)
+            so, co = oracle.sincos(x, arith, method)
+            assert_bit_exact(sg, so, "sin", x)
+            assert_bit_exact(cg, co, "cos", x)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_contract_mode_within_stated_bound(torch_dev, method):
+    """With contraction allowed the compiler may fuse any product into its
+    sum; each component stays within 2^-20 of the split oracle."""
+    x = np.concatenate([
+        np.random.default_rng(8).uniform(-8 * math.pi, 8 * math.pi, 1 << 20),
+        np.random.default_rng(9).uniform(-1e4, 1e4, 1 << 20)]).astype(np.float32)
+    sg, cg = run(torch_dev, x, CONTRACT, method)
+    so, co = oracle.sincos(x, SPLIT, method, threads=oracle.default_threads())
+    ds = np.abs(sg.astype(np.float64) - so)
+    dc = np.abs(cg.astype(np.float64) - co)
+    log("contract vs split: max |ds| %.3g, max |dc| %.3g, %.2f%% differ" % (
+        ds.max(), dc.max(), 100 * np.mean((ds > 0) | (dc > 0))))
+    assert ds.max() <= 2.0 ** -20 and dc.max() <= 2.0 ** -20
+
+
+def test_gpu_accuracy_matches_paper(torch_dev):
+    """The GPU pairs themselves reproduce the printed RMS error (uniform angles
+    in [-pi, pi) against the double library)."""
+    x = np.random.default_rng(7).uniform(-math.pi, math.pi, 1 << 22).astype(np.float32)
+    sg, cg = run(torch_dev, x, FUSED, 0)
+    xd = x.astype(np.float64)
+    e = np.sqrt((sg - np.sin(xd)) ** 2 + (cg - np.cos(xd)) ** 2)
+    rms = float(np.sqrt(np.mean(e ** 2)))
+    log("GPU RMS vector error %.3g (paper 1.2e-7), max %.3g" % (rms, e.max()))
+    assert abs(rms / 1.2e-7 - 1) < 0.05
