@@ -61,8 +61,10 @@ typedef enum {
  * SPLIT: every product and every sum is rounded on its own (the same
  *        expression tree, built with floating-point contraction off).
  * CONTRACT: the SPLIT expression tree compiled with contraction allowed; the
- *        compiler may fuse any product into a following sum.  Results are
- *        within 2^-20 (absolute, per component) of SPLIT.
+ *        compiler may fuse any product into a following sum.  Each component
+ *        is within 2^-20 + pi * ulp(fl(x / (2 pi))) (absolute) of SPLIT: the
+ *        second term is the rounding of the scaled angle, which a fused
+ *        reduction skips.
  * FUSED and SPLIT are bit-exact against the CPU oracle of the same mode. */
 typedef enum {
     SINCOS_ARITH_FUSED = 0,

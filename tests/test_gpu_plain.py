@@ -1,5 +1,5 @@
 """Plain form on the GPU against the CPU oracle: bit-exact in FUSED and SPLIT
-arithmetic (NaN compared as NaN), within 2^-20 for CONTRACT."""
+arithmetic (NaN compared as NaN), within the stated bound for CONTRACT."""
 import math
 
 import numpy as np
@@ -166,18 +166,28 @@ def test_special_values(torch_dev):
 
 @pytest.mark.parametrize("method", [0, 1])
 def test_contract_mode_within_stated_bound(torch_dev, method):
-    """With contraction allowed the compiler may fuse any product into its
-    sum; each component stays within 2^-20 of the split oracle."""
+    """With contraction allowed the compiler may fuse any product into the sum
+    that consumes it.  Fusing x*K into the reduction x1 - rint(x1) skips the
+    rounding of x1, which moves the reduced angle by at most ulp(x1)/2 turns,
+    i.e. pi*ulp(x1) radians; every other fusion changes a component by less
+    than 2^-20.  Bound per component: 2^-20 + pi*ulp(fl(x*K))."""
     x = np.concatenate([
         np.random.default_rng(8).uniform(-8 * math.pi, 8 * math.pi, 1 << 20),
-        np.random.default_rng(9).uniform(-1e4, 1e4, 1 << 20)]).astype(np.float32)
+        np.random.default_rng(9).uniform(-1e4, 1e4, 1 << 20),
+        np.random.default_rng(10).uniform(-0.5, 0.5, 1 << 18)]).astype(np.float32)
     sg, cg = run(torch_dev, x, CONTRACT, method)
     so, co = oracle.sincos(x, SPLIT, method, threads=oracle.default_threads())
+    k = np.float32(1.0 / (2.0 * 3.1415926536))
+    x1 = np.abs((x * k).astype(np.float32))
+    ulp = (np.nextafter(x1, np.float32(np.inf)) - x1).astype(np.float64)
+    bound = 2.0 ** -20 + math.pi * np.where(x1 == 0, 0.0, ulp)
     ds = np.abs(sg.astype(np.float64) - so)
     dc = np.abs(cg.astype(np.float64) - co)
-    log("contract vs split: max |ds| %.3g, max |dc| %.3g, %.2f%% differ" % (
-        ds.max(), dc.max(), 100 * np.mean((ds > 0) | (dc > 0))))
-    assert ds.max() <= 2.0 ** -20 and dc.max() <= 2.0 ** -20
+    small = np.abs(x) < 4.0
+    log("contract vs split: max |ds| %.3g, max |dc| %.3g (|x| < 4: %.3g), %.2f%% differ" % (
+        ds.max(), dc.max(), max(ds[small].max(), dc[small].max()),
+        100 * np.mean((ds > 0) | (dc > 0))))
+    assert np.all(ds <= bound) and np.all(dc <= bound)
 
 
 def test_gpu_accuracy_matches_paper(torch_dev):
