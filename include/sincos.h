@@ -52,7 +52,9 @@ typedef enum {
     SINCOS_EOVERLAP = -2, /* forbidden aliasing between inputs and outputs    */
     SINCOS_ENOMEM = -3,   /* a library-owned device or host buffer failed     */
     SINCOS_EHIP = -4,     /* the HIP runtime returned an error                */
-    SINCOS_ENODEV = -5    /* no usable gfx950 device is current               */
+    SINCOS_ENODEV = -5,   /* no usable gfx950 device is current               */
+    SINCOS_ECANCELED = -6, /* request dropped because its server shut down    */
+    SINCOS_EBUDGET = -7   /* request larger than the server's whole budget   */
 } sincos_status_t;
 
 /* Arithmetic of the multiply-adds.
@@ -188,6 +190,82 @@ SINCOS_API int sinusoid_f32_backward(const float *t, const float *g, int64_t N, 
  * ceiling for the plain kernel.                                           */
 SINCOS_API int sincos_copy_ceiling_f32(const float *x, float *s, float *c, int64_t n,
                             const sincos_launch_t *launch, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Request server: continuous batching of sine-cosine requests of any size.
+ *
+ * A scheduler thread owns an output arena in device memory and up to
+ * `max_inflight` streams.  Submitted requests queue in arrival order; a
+ * request is admitted when its 12 n bytes fit in the HBM budget (4 n for the
+ * input it pins, 8 n for its outputs) and an arena block is free.  Whenever
+ * a stream is free, every admitted request not yet launched (up to the
+ * batch caps) goes to the device as ONE ragged launch, so requests that
+ * arrive while others run join the next batch and batches overlap on the
+ * device.  A completion carries the device addresses of the request's
+ * outputs; they stay valid until the request is released (or at once with
+ * auto_release).  Release returns the request's budget and arena block.
+ * Each result is the same bits as a plain sincos_f32 call on the same input
+ * (the kernels share the arithmetic).
+ * Times are host steady-clock nanoseconds.  Inputs are device pointers owned
+ * by the caller, which keeps them unchanged until the request completes.  */
+typedef struct sincos_server sincos_server_t;
+
+typedef struct {
+    int64_t budget_bytes;       /* HBM admission budget (0 = 8 GiB)                     */
+    int32_t max_inflight;       /* batches on the device at once (0 = 4, max 16)        */
+    int32_t max_batch_requests; /* requests per batch (0 = 4096)                        */
+    int64_t max_batch_elems;    /* elements per batch (0 = no cap)                      */
+    int32_t arith;              /* sincos_arith_t                                        */
+    int32_t method;             /* sincos_method_t                                       */
+    int32_t mode;               /* 0 = continuous batching (one ragged launch per batch),
+                                   1 = one plain launch per request (the baseline)       */
+    int32_t executor;           /* 0 = the GPU; 1 = simulated (no device work, no device
+                                   memory; completion after sim_* time; host tests)     */
+    int64_t sim_batch_ns;       /* simulated: fixed time per batch                      */
+    int64_t sim_elem_ps;        /* simulated: picoseconds per element                   */
+    int32_t sim_fail_every;     /* simulated: every k-th batch fails (0 = never)        */
+    int32_t auto_release;       /* 1 = free a request's outputs as soon as it completes */
+} sincos_server_config_t;
+
+typedef struct {
+    int64_t id;
+    uint64_t tag;
+    int32_t status;             /* SINCOS_OK, SINCOS_EHIP (batch failed), SINCOS_ECANCELED */
+    int32_t batch_requests;     /* requests in the batch that carried it                 */
+    const float *s;             /* device outputs, n each (NULL with auto_release)       */
+    const float *c;
+    int64_t n;
+    int64_t t_submit_ns, t_admit_ns, t_launch_ns, t_complete_ns;
+} sincos_completion_t;
+
+typedef struct {
+    int64_t submitted, admitted, completed, failed, batches;
+    int64_t elements_completed;
+    int64_t budget_in_use, budget_peak;
+    int32_t inflight_peak;
+    int32_t reserved;
+} sincos_server_stats_t;
+
+SINCOS_API int sincos_server_create(const sincos_server_config_t *cfg, sincos_server_t **out);
+/* Queue a request of n >= 1 elements; *out_id receives its id.  Returns
+ * SINCOS_EBUDGET if 12 n exceeds the whole budget.  Thread-safe.          */
+SINCOS_API int sincos_server_submit(sincos_server_t *srv, const float *x, int64_t n, uint64_t tag,
+                                    int64_t *out_id);
+/* Up to `max` completions (waits up to timeout_ns for the first one).     */
+SINCOS_API int sincos_server_poll(sincos_server_t *srv, sincos_completion_t *out, int32_t max,
+                                  int32_t *count, int64_t timeout_ns);
+/* Give back a completed request's outputs and budget.                     */
+SINCOS_API int sincos_server_release(sincos_server_t *srv, int64_t id);
+SINCOS_API int sincos_server_stats(const sincos_server_t *srv, sincos_server_stats_t *out);
+/* Submit request j at start + arrival_ns[j] from a generator thread, wait
+ * for every completion and store it in out[j].  With auto_release off each
+ * request is released once its completion is stored.                     */
+SINCOS_API int sincos_server_replay(sincos_server_t *srv, const float *const *xs,
+                                    const int64_t *ns, const int64_t *arrival_ns, int32_t count,
+                                    sincos_completion_t *out);
+/* Stop: pending (unadmitted) requests complete with SINCOS_ECANCELED,
+ * batches on the device are waited for, then everything is freed.        */
+SINCOS_API int sincos_server_destroy(sincos_server_t *srv);
 
 /* ---------------------------------------------------------------------- */
 /* Message for the last non-OK status returned on this thread ("" if none). */

@@ -16,10 +16,11 @@ import threading
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmi355_sincos.so")
 
-OK, EINVAL, EOVERLAP, ENOMEM, EHIP, ENODEV = 0, -1, -2, -3, -4, -5
+OK, EINVAL, EOVERLAP, ENOMEM, EHIP, ENODEV, ECANCELED, EBUDGET = 0, -1, -2, -3, -4, -5, -6, -7
 ARITH_FUSED, ARITH_SPLIT, ARITH_CONTRACT = 0, 1, 2
 METHOD_NORMALIZED, METHOD_ARCTAN = 0, 1
-STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EOVERLAP", -3: "ENOMEM", -4: "EHIP", -5: "ENODEV"}
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EOVERLAP", -3: "ENOMEM", -4: "EHIP", -5: "ENODEV",
+                -6: "ECANCELED", -7: "EBUDGET"}
 
 
 class SincosError(RuntimeError):
@@ -36,6 +37,31 @@ class Launch(ctypes.Structure):
 
 class Seg(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("s", ctypes.c_void_p), ("c", ctypes.c_void_p)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("max_batch_requests", ctypes.c_int32), ("max_batch_elems", ctypes.c_int64),
+                ("arith", ctypes.c_int32), ("method", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("executor", ctypes.c_int32), ("sim_batch_ns", ctypes.c_int64),
+                ("sim_elem_ps", ctypes.c_int64), ("sim_fail_every", ctypes.c_int32),
+                ("auto_release", ctypes.c_int32)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("batch_requests", ctypes.c_int32), ("s", ctypes.c_void_p),
+                ("c", ctypes.c_void_p), ("n", ctypes.c_int64), ("t_submit_ns", ctypes.c_int64),
+                ("t_admit_ns", ctypes.c_int64), ("t_launch_ns", ctypes.c_int64),
+                ("t_complete_ns", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("admitted", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("elements_completed", ctypes.c_int64),
+                ("budget_in_use", ctypes.c_int64), ("budget_peak", ctypes.c_int64),
+                ("inflight_peak", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lock = threading.Lock()
@@ -66,6 +92,16 @@ _SIGNATURES = {
     "sinusoid_f32_backward": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _P, _P, _P, _P, _I64,
                                              _P]),
     "sincos_copy_ceiling_f32": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(Launch), _P]),
+    "sincos_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)]),
+    "sincos_server_submit": (ctypes.c_int, [_P, _P, _I64, ctypes.c_uint64, ctypes.POINTER(_I64)]),
+    "sincos_server_poll": (ctypes.c_int, [_P, ctypes.POINTER(Completion), _I32,
+                                          ctypes.POINTER(_I32), _I64]),
+    "sincos_server_release": (ctypes.c_int, [_P, _I64]),
+    "sincos_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(ServerStats)]),
+    "sincos_server_replay": (ctypes.c_int, [_P, ctypes.POINTER(_P), ctypes.POINTER(_I64),
+                                            ctypes.POINTER(_I64), _I32,
+                                            ctypes.POINTER(Completion)]),
+    "sincos_server_destroy": (ctypes.c_int, [_P]),
     "sincos_last_error": (ctypes.c_char_p, []),
     "sincos_version": (ctypes.c_char_p, []),
 }

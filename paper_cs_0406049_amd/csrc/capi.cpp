@@ -216,31 +216,26 @@ static int check_ragged(const sincos_seg_t *segs, const int64_t *lens, int32_t c
     return check_ragged_aliasing(segs, lens, count);
 }
 
-// Host table of a ragged batch: descriptors of the non-empty segments, then
-// their first-unit offsets (count + 1 entries).
-struct RaggedTable {
-    std::vector<RaggedDesc> desc;
-    std::vector<int64_t> ubeg;
-    int64_t elements = 0;
-};
+void table_add(RaggedTable &t, const float *x, float *s, float *c, int64_t n,
+               const LaunchShape &sh)
+{
+    if (t.ubeg.empty())
+        t.ubeg.push_back(0);
+    RaggedDesc d = make_desc(x, s, c, n);
+    t.desc.push_back(d);
+    t.ubeg.push_back(t.ubeg.back() + ragged_units(d, sh));
+    t.elements += n;
+}
 
 static void build_table(const sincos_seg_t *segs, const int64_t *lens, int32_t count,
                         const LaunchShape &sh, RaggedTable &t)
 {
     t.desc.clear();
-    t.ubeg.clear();
+    t.ubeg.assign(1, 0);
     t.elements = 0;
-    int64_t u = 0;
-    for (int32_t j = 0; j < count; ++j) {
-        if (lens[j] == 0)
-            continue;
-        RaggedDesc d = make_desc(segs[j].x, segs[j].s, segs[j].c, lens[j]);
-        t.desc.push_back(d);
-        t.ubeg.push_back(u);
-        u += ragged_units(d, sh);
-        t.elements += lens[j];
-    }
-    t.ubeg.push_back(u);
+    for (int32_t j = 0; j < count; ++j)
+        if (lens[j] > 0)
+            table_add(t, segs[j].x, segs[j].s, segs[j].c, lens[j], sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -248,9 +243,7 @@ static void build_table(const sincos_seg_t *segs, const int64_t *lens, int32_t c
 // slot, reused once the event recorded after its last use has completed.
 
 struct StageSlot {
-    char *host = nullptr;
-    char *dev = nullptr;
-    size_t cap = 0;
+    StagingBuffers buf;
     hipEvent_t done = nullptr;
     bool pending = false;
 };
@@ -276,8 +269,13 @@ static StageRing &ring_for(int device)
     return *r;
 }
 
-int ragged_enqueue(const RaggedTable &t, int arith, int method, const LaunchShape &shape,
-                   const DeviceInfo &dev, hipStream_t stream)
+size_t staged_bytes(const RaggedTable &t)
+{
+    return sizeof(RaggedDesc) * t.desc.size() + sizeof(int64_t) * t.ubeg.size();
+}
+
+int stage_and_launch(const RaggedTable &t, char *host, char *dev_buf, int arith, int method,
+                     const LaunchShape &shape, const DeviceInfo &dev, hipStream_t stream)
 {
     const int32_t count = (int32_t)t.desc.size();
     if (count == 0)
@@ -285,8 +283,58 @@ int ragged_enqueue(const RaggedTable &t, int arith, int method, const LaunchShap
     const int64_t total = t.ubeg.back();
     const LaunchShape sh = resolve_ragged_shape(shape, total, dev);
     const size_t desc_bytes = sizeof(RaggedDesc) * (size_t)count;
-    const size_t bytes = desc_bytes + sizeof(int64_t) * (size_t)(count + 1);
+    const size_t bytes = staged_bytes(t);
+    std::memcpy(host, t.desc.data(), desc_bytes);
+    std::memcpy(host + desc_bytes, t.ubeg.data(), sizeof(int64_t) * (size_t)(count + 1));
+    hipError_t e = hipMemcpyAsync(dev_buf, host, bytes, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess)
+        return hip_error(e, "ragged: staging copy");
+    e = launch_ragged(reinterpret_cast<const RaggedDesc *>(dev_buf),
+                      reinterpret_cast<const int64_t *>(dev_buf + desc_bytes), count, total, arith,
+                      method, sh, stream);
+    if (e != hipSuccess)
+        return hip_error(e, "ragged: kernel launch");
+    return SINCOS_OK;
+}
 
+int grow_staging(StagingBuffers &b, size_t bytes)
+{
+    if (b.cap >= bytes)
+        return SINCOS_OK;
+    if (b.host)
+        (void)hipHostFree(b.host);
+    if (b.dev)
+        (void)hipFree(b.dev);
+    b.host = nullptr;
+    b.dev = nullptr;
+    b.cap = 0;
+    const size_t cap = std::max<size_t>(bytes, 64 * 1024);
+    if (hipHostMalloc((void **)&b.host, cap, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void **)&b.dev, cap) != hipSuccess) {
+        if (b.host)
+            (void)hipHostFree(b.host);
+        b.host = nullptr;
+        b.dev = nullptr;
+        return set_error(SINCOS_ENOMEM, "ragged: cannot allocate the staging buffers");
+    }
+    b.cap = cap;
+    return SINCOS_OK;
+}
+
+void free_staging(StagingBuffers &b)
+{
+    if (b.host)
+        (void)hipHostFree(b.host);
+    if (b.dev)
+        (void)hipFree(b.dev);
+    b = StagingBuffers{};
+}
+
+int ragged_enqueue(const RaggedTable &t, int arith, int method, const LaunchShape &shape,
+                   const DeviceInfo &dev, hipStream_t stream)
+{
+    if (t.desc.empty())
+        return SINCOS_OK;
     StageRing &ring = ring_for(dev.device);
     std::lock_guard<std::mutex> lk(ring.mu);
     StageSlot &slot = ring.slots[ring.next];
@@ -298,37 +346,14 @@ int ragged_enqueue(const RaggedTable &t, int arith, int method, const LaunchShap
             return hip_error(e, "ragged: waiting for a staging slot");
         slot.pending = false;
     }
-    if (slot.cap < bytes) {
-        if (slot.host)
-            (void)hipHostFree(slot.host);
-        if (slot.dev)
-            (void)hipFree(slot.dev);
-        slot.host = nullptr;
-        slot.dev = nullptr;
-        slot.cap = 0;
-        size_t cap = std::max<size_t>(bytes, 64 * 1024);
-        if (hipHostMalloc((void **)&slot.host, cap, hipHostMallocDefault) != hipSuccess ||
-            hipMalloc((void **)&slot.dev, cap) != hipSuccess) {
-            if (slot.host)
-                (void)hipHostFree(slot.host);
-            slot.host = nullptr;
-            slot.dev = nullptr;
-            return set_error(SINCOS_ENOMEM, "ragged: cannot allocate the staging buffers");
-        }
-        slot.cap = cap;
-    }
+    int rc = grow_staging(slot.buf, staged_bytes(t));
+    if (rc != SINCOS_OK)
+        return rc;
     if (!slot.done && hipEventCreateWithFlags(&slot.done, hipEventDisableTiming) != hipSuccess)
         return set_error(SINCOS_EHIP, "ragged: cannot create an event");
-    std::memcpy(slot.host, t.desc.data(), desc_bytes);
-    std::memcpy(slot.host + desc_bytes, t.ubeg.data(), sizeof(int64_t) * (size_t)(count + 1));
-    e = hipMemcpyAsync(slot.dev, slot.host, bytes, hipMemcpyHostToDevice, stream);
-    if (e != hipSuccess)
-        return hip_error(e, "ragged: staging copy");
-    e = launch_ragged(reinterpret_cast<const RaggedDesc *>(slot.dev),
-                      reinterpret_cast<const int64_t *>(slot.dev + desc_bytes), count, total, arith,
-                      method, sh, stream);
-    if (e != hipSuccess)
-        return hip_error(e, "ragged: kernel launch");
+    rc = stage_and_launch(t, slot.buf.host, slot.buf.dev, arith, method, shape, dev, stream);
+    if (rc != SINCOS_OK)
+        return rc;
     e = hipEventRecord(slot.done, stream);
     if (e != hipSuccess)
         return hip_error(e, "ragged: event record");

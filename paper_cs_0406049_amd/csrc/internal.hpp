@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 namespace mi355 {
 
@@ -63,6 +64,36 @@ RaggedDesc make_desc(const float *x, float *s, float *c, int64_t n);
 LaunchShape resolve_plain_shape(const LaunchShape &req, int64_t n, const DeviceInfo &dev);
 LaunchShape resolve_ragged_shape(const LaunchShape &req, int64_t total_units,
                                  const DeviceInfo &dev);
+
+// Host table of a ragged batch: descriptors of the non-empty segments, then
+// their first-unit offsets (count + 1 entries).
+struct RaggedTable {
+    std::vector<RaggedDesc> desc;
+    std::vector<int64_t> ubeg;
+    int64_t elements = 0;
+};
+// Append one segment (n > 0) to a table under construction.
+void table_add(RaggedTable &t, const float *x, float *s, float *c, int64_t n,
+               const LaunchShape &shape);
+// Pinned host + device buffers for one staged descriptor table.
+struct StagingBuffers {
+    char *host = nullptr;
+    char *dev = nullptr;
+    size_t cap = 0;
+};
+size_t staged_bytes(const RaggedTable &t);
+// Make b hold at least `bytes` (reallocates; the caller knows b is idle).
+int grow_staging(StagingBuffers &b, size_t bytes);
+void free_staging(StagingBuffers &b);
+// Copy the table into `host`, enqueue its copy to `dev_buf` and the ragged
+// kernel on `stream`.  The buffers must stay untouched until the stream has
+// passed the launch.
+int stage_and_launch(const RaggedTable &t, char *host, char *dev_buf, int arith, int method,
+                     const LaunchShape &shape, const DeviceInfo &dev, hipStream_t stream);
+// Stage the table through the library's pinned/device ring and launch the
+// ragged kernel on `stream`.  Returns a sincos status.
+int ragged_enqueue(const RaggedTable &t, int arith, int method, const LaunchShape &shape,
+                   const DeviceInfo &dev, hipStream_t stream);
 
 // Thread-local error reporting used by every C entry point.
 int set_error(int status, const std::string &msg);
