@@ -96,6 +96,122 @@ def cpu_baseline(x_host, arith: int):
                                                            threads, dt)}
 
 
+# ---------------------------------------------------------------------------
+# The forms built around the plain kernel, each against its per-call baseline.
+
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # lane-ops/s without packed FP32: 39.3 T
+SINUSOID_FWD_OPS = 23   # VALU ops per (sample, frequency) pair, forward
+SINUSOID_ADJ_OPS = 29   # VALU ops per pair, adjoint (pair + three accumulations)
+
+
+def bench_ragged(torch, reps, plain_gbs):
+    from paper_cs_0406049_amd import _capi, autotune, workloads
+    lens, xs_h = workloads.ragged_batch()
+    segs = []
+    for xh in xs_h:
+        x = torch.from_numpy(xh).cuda()
+        segs.append((x, torch.empty_like(x), torch.empty_like(x)))
+    del xs_h
+    elems = int(lens.sum())
+    shape = autotune.tune_ragged(segs, lens, cache_path=None, reps=3)
+    plan = _capi.RaggedPlan(segs, lens, launch=shape)
+    g_ms, _ = time_launches(torch, plan.graph_launch, reps, 2)
+    k_ms, _ = time_launches(torch, plan.launch, reps, 2)
+    one_ms, _ = time_launches(torch, lambda: _capi.sincos_f32_ragged(segs, lens), reps, 2)
+
+    def per_array():
+        for x, s_, c_ in segs:
+            _capi.sincos_f32(x, s_, c_, x.numel())
+    pa_ms, _ = time_launches(torch, per_array, max(2, reps // 5), 1)
+    gbs = BYTES_PER_ELEM * elems / (g_ms * 1e-3) / 1e9
+    plan.destroy()
+    return {"workload": "4096 arrays, lengths log-uniform in [100, 1e6] (seed 2), %d elements, "
+                        "angles U[-100 pi, 100 pi)" % elems,
+            "autotuned_launch": {"block": shape[0], "unroll": shape[1], "grid": shape[2]},
+            "graph_ms": round(g_ms, 4), "kernel_ms": round(k_ms, 4),
+            "oneshot_staged_ms": round(one_ms, 4), "per_array_plain_ms": round(pa_ms, 4),
+            "gelem_s": round(elems / (g_ms * 1e-3) / 1e9, 2), "GBps": round(gbs, 1),
+            "per_byte_vs_plain": round(gbs / plain_gbs, 4),
+            "speedup_vs_per_array": round(pa_ms / g_ms, 2)}
+
+
+def bench_sinusoid(torch, reps):
+    from paper_cs_0406049_amd import _capi, workloads
+    from paper_cs_0406049_amd.autograd import sinusoid_loss_and_grads
+    p = workloads.sinusoid_problem()
+    d = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+    t, A, w, phi, yobs = d(p.t), d(p.A), d(p.w), d(p.phi), d(p.y_obs)
+    N, K = t.numel(), A.numel()
+    y = torch.empty_like(t)
+    f_ms, _ = time_launches(torch, lambda: _capi.sinusoid_f32_forward(t, A, w, phi, y), reps, 2)
+    r = y - yobs
+    gA, gw, gp = torch.empty_like(A), torch.empty_like(A), torch.empty_like(A)
+    nb = _capi.sinusoid_f32_backward_workspace_bytes(N, K)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    a_ms, _ = time_launches(torch, lambda: _capi.sinusoid_f32_backward(
+        t, r, A, w, phi, gA, gw, gp, ws, nb), reps, 2)
+    tot_ms, _ = time_launches(torch, lambda: sinusoid_loss_and_grads(t, yobs, A, w, phi), reps, 2)
+    # composed baseline: theta matrix in torch, the plain kernel over it, then
+    # rocBLAS products for the model and its gradients
+    theta = torch.empty(K, N, device="cuda")
+    S = torch.empty_like(theta)
+    C = torch.empty_like(theta)
+
+    def composed():
+        torch.addcmul(phi[:, None], w[:, None], t[None, :], out=theta)
+        _capi.sincos_f32(theta, S, C, theta.numel())
+        yy = A @ S
+        rr = yy - yobs
+        return 0.5 * torch.dot(rr, rr), S @ rr, A * (C @ (rr * t)), A * (C @ rr)
+    c_ms, _ = time_launches(torch, composed, reps, 2)
+    pairs = N * K
+    ops = pairs * (SINUSOID_FWD_OPS + SINUSOID_ADJ_OPS)
+    del theta, S, C
+    return {"workload": "y(t) = sum_k A_k sin(w_k t + phi_k), N = %d samples, K = %d, loss "
+                        "1/2 sum (y - y_obs)^2, forward + adjoint" % (N, K),
+            "forward_ms": round(f_ms, 4), "adjoint_ms": round(a_ms, 4),
+            "loss_and_grads_ms": round(tot_ms, 4), "composed_plain_kernel_plus_torch_ms":
+            round(c_ms, 4), "speedup_vs_composed": round(c_ms / tot_ms, 2),
+            "pairs_per_s": round(2 * pairs / (tot_ms * 1e-3), 1),
+            "roofline": {"bound": "alu", "achieved": round(ops / (tot_ms * 1e-3) / 1e12, 2),
+                         "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s (VALU lane-ops)",
+                         "frac": round(ops / (tot_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4),
+                         "ops_per_pair": [SINUSOID_FWD_OPS, SINUSOID_ADJ_OPS]}}
+
+
+def bench_serve(torch, plain_gelem_s):
+    import numpy as np
+    from paper_cs_0406049_amd import serve, workloads
+    rs = workloads.request_stream()
+    pool = torch.from_numpy(rs.pool).cuda()
+    assert int((rs.offsets + rs.sizes).max()) <= pool.numel()
+    xs = [pool.data_ptr() + 4 * int(o) for o in rs.offsets]
+    mean_n = float(rs.sizes.mean())
+    rate = 0.7 * plain_gelem_s * 1e9 / mean_n
+    arr = (np.cumsum(rs.unit_gaps) / rate * 1e9).astype(np.int64)
+    arr -= arr[0]
+    out = {"workload": "%d requests, sizes log-uniform in [1e3, 1e7] (seed 4, mean %.0f), "
+                       "Poisson arrivals at 70%% of the plain kernel's rate (%.0f req/s), "
+                       "budget 8 GiB, inputs resident in HBM" % (rs.sizes.size, mean_n, rate)}
+    for name, mode in (("batched", serve.MODE_BATCHED), ("per_request", serve.MODE_PER_REQUEST)):
+        with serve.Server(mode=mode, max_inflight=4, auto_release=True) as srv:
+            srv.replay(xs[:200], rs.sizes[:200], np.zeros(200, np.int64))   # warm
+            comp = srv.replay(xs, rs.sizes, arr)
+            summ = serve.latency_summary(comp)
+            summ["batches"] = srv.stats()["batches"]
+        closed = None
+        with serve.Server(mode=mode, max_inflight=4, auto_release=True) as srv:
+            comp = srv.replay(xs, rs.sizes, np.zeros(rs.sizes.size, np.int64))
+            closed = serve.latency_summary(comp)
+        summ["saturation_gelem_s"] = round(closed["throughput_gelem_s"], 2)
+        summ["saturation_per_byte_vs_plain"] = round(closed["throughput_gelem_s"] / plain_gelem_s, 4)
+        out[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
+        log("serve %s: p50 %.1f us, p99 %.1f us, %.1f Gelem/s delivered, saturation %.1f" % (
+            name, summ["p50_us"], summ["p99_us"], summ["throughput_gelem_s"],
+            summ["saturation_gelem_s"]))
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +224,8 @@ def main(argv=None):
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceiling", action="store_true")
+    ap.add_argument("--forms", default="ragged,sinusoid,serve",
+                    help="comma list of forms to measure after the plain kernel ('' = none)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -196,6 +314,20 @@ def main(argv=None):
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(x_host, arith)
+    forms = [f for f in args.forms.split(",") if f]
+    if forms:
+        del x, s, c
+        torch.cuda.empty_cache()
+        out["forms"] = {}
+    for f in forms:
+        log("form: %s" % f)
+        if f == "ragged":
+            out["forms"]["ragged"] = bench_ragged(torch, max(5, args.steps // 4), achieved)
+        elif f == "sinusoid":
+            out["forms"]["sinusoid"] = bench_sinusoid(torch, max(5, args.steps // 4))
+        elif f == "serve":
+            out["forms"]["serve"] = bench_serve(torch, value)
+        torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
     return 0
 

@@ -116,6 +116,13 @@ def lib():
                 raise RuntimeError(
                     "libmi355_sincos.so is not built (python -m paper_cs_0406049_amd.build); "
                     "this package has no CPU or fallback path")
+            # PyTorch-ROCm ships its own HIP runtime under the same soname.  Load
+            # torch first so the library binds to that one runtime: device
+            # pointers and streams from torch are then valid here.
+            try:
+                import torch  # noqa: F401
+            except ImportError:
+                pass
             L = ctypes.CDLL(LIB_PATH)
             for name, (res, args) in _SIGNATURES.items():
                 fn = getattr(L, name)

@@ -1,0 +1,113 @@
+"""Launch-shape autotuner for the ragged form.
+
+For a ragged batch it times one plan per candidate (block, unroll, grid) with
+HIP events (the kernel only, each candidate replayed a few times after a
+warm-up), keeps the fastest, and caches the choice in a JSON file keyed by
+device architecture, CU count and a bucket of the batch's size (segment count
+and total elements, each rounded to a power of two), so a later batch of a
+similar size reuses it without timing.
+
+    shape = autotune.tune_ragged(segs, lens)        # (block, unroll, grid)
+    plan = _capi.RaggedPlan(segs, lens, launch=shape)
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import threading
+
+from . import _capi
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mi355_sincos", "tune.json")
+
+BLOCKS = (256, 512, 1024)
+UNROLLS = (1, 2, 4, 8)
+WAVES_PER_CU = (4, 8, 16, 32)   # persistent grid = CUs * this / (block / 256)
+
+_lock = threading.Lock()
+
+
+def _bucket(v: int) -> int:
+    return 0 if v <= 0 else 1 << int(math.ceil(math.log2(v)))
+
+
+def cache_key(arch: str, cus: int, count: int, elements: int, arith: int, method: int) -> str:
+    return "%s/cu%d/ragged/a%d-m%d/seg%d/el%d" % (arch, cus, arith, method, _bucket(count),
+                                                 _bucket(elements))
+
+
+def load_cache(path: str = DEFAULT_CACHE) -> dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(cache: dict, path: str = DEFAULT_CACHE) -> None:
+    d = os.path.dirname(path)
+    if d:
+        os.makedirs(d, exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def candidates(cus: int):
+    for block in BLOCKS:
+        for unroll in UNROLLS:
+            for wpc in WAVES_PER_CU:
+                grid = max(1, cus * wpc * 256 // block // 4)
+                yield (block, unroll, grid)
+
+
+def time_plan(torch, plan, reps: int = 5) -> float:
+    """Average milliseconds of one plan launch (kernel only)."""
+    plan.launch()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    st = torch.cuda.current_stream()
+    a.record(st)
+    for _ in range(reps):
+        plan.launch()
+    b.record(st)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tune_ragged(segs, lens=None, arith: int = _capi.ARITH_FUSED,
+                method: int = _capi.METHOD_NORMALIZED, cache_path: str | None = DEFAULT_CACHE,
+                force: bool = False, reps: int = 5, verbose: bool = False):
+    """Best (block, unroll, grid) for this batch (from the cache if present).
+    The arrays' contents are overwritten with valid outputs while timing."""
+    import torch
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(props, "gcnArchName", "unknown").split(":")[0]
+    cus = props.multi_processor_count
+    if lens is None:
+        lens = [int(x.numel()) for x, _, _ in segs]
+    key = cache_key(arch, cus, len(lens), int(sum(lens)), arith, method)
+    with _lock:
+        cache = load_cache(cache_path) if cache_path else {}
+        if not force and key in cache:
+            return tuple(cache[key]["shape"])
+    results = []
+    for shape in candidates(cus):
+        plan = _capi.RaggedPlan(segs, lens, arith, method, launch=shape)
+        ms = time_plan(torch, plan, reps)
+        plan.destroy()
+        results.append((ms, shape))
+        if verbose:
+            print("autotune %-18s %.4f ms" % (shape, ms), flush=True)
+    results.sort()
+    best_ms, best = results[0]
+    if cache_path:
+        with _lock:
+            cache = load_cache(cache_path)
+            cache[key] = {"shape": list(best), "ms": best_ms, "elements": int(sum(lens)),
+                          "segments": len(lens), "tried": len(results)}
+            save_cache(cache, cache_path)
+    return best

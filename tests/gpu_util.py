@@ -32,3 +32,16 @@ def assert_bit_exact(got, want, what="", x=None):
 
 def log(msg):
     print(msg, flush=True)
+
+
+class _DeviceArray:
+    """Exposes a device address as a float32 array (CUDA array interface)."""
+
+    def __init__(self, ptr, n):
+        self.__cuda_array_interface__ = {"shape": (int(n),), "typestr": "<f4",
+                                         "data": (int(ptr), False), "version": 2}
+
+
+def device_view(torch, ptr, n):
+    """A float32 tensor aliasing n elements at a device address."""
+    return torch.as_tensor(_DeviceArray(ptr, n), device="cuda")

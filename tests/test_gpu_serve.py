@@ -1,0 +1,84 @@
+"""The request server on the GPU: every result in the mix is the same bits
+as the same request alone (plain call) and as the oracle; batches overlap."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_bit_exact, device_view, lib_loaded, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lib_loaded()
+    return torch
+
+
+def _pool(torch, elems, seed):
+    xh = np.random.default_rng(seed).uniform(-1e3, 1e3, elems).astype(np.float32)
+    return xh, torch.from_numpy(xh).cuda()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_mix_equals_alone(torch_dev, mode):
+    torch = torch_dev
+    from paper_cs_0406049_amd import _capi, serve
+    xh, pool = _pool(torch, 1 << 22, 1)
+    rng = np.random.default_rng(2)
+    sizes = np.floor(10 ** rng.uniform(0, 5.5, 300)).astype(np.int64)
+    offs = rng.integers(0, pool.numel() - sizes.max() - 4, 300)
+    offs[::5] += rng.integers(1, 4, offs[::5].size)   # some inputs off the 16-byte grid
+    assert np.all(offs >= 0) and np.all(offs + sizes <= pool.numel())
+    base = pool.data_ptr()
+    with serve.Server(max_inflight=3, mode=mode) as srv:
+        ids = [srv.submit(base + 4 * int(o), int(n), tag=j) for j, (o, n) in enumerate(zip(offs, sizes))]
+        comps = []
+        while len(comps) < len(ids):
+            comps += srv.poll(256, 1.0)
+        st = srv.stats()
+        for c in comps:
+            assert c.status == _capi.OK
+            j = int(c.tag)
+            n, o = int(sizes[j]), int(offs[j])
+            s_alone = torch.empty(n, device="cuda")
+            c_alone = torch.empty(n, device="cuda")
+            _capi.sincos_f32(base + 4 * o, s_alone, c_alone, n)
+            torch.cuda.synchronize()
+            s_mix = device_view(torch, c.s, n).clone()
+            c_mix = device_view(torch, c.c, n).clone()
+            torch.cuda.synchronize()
+            assert torch.equal(s_mix.view(torch.int32), s_alone.view(torch.int32)), j
+            assert torch.equal(c_mix.view(torch.int32), c_alone.view(torch.int32)), j
+            if j % 25 == 0:
+                so, co = oracle.sincos(xh[o:o + n], 0, 0)
+                assert_bit_exact(s_mix.cpu().numpy(), so, "served sin %d" % j)
+                assert_bit_exact(c_mix.cpu().numpy(), co, "served cos %d" % j)
+            srv.release(c.id)
+        log("mode %d: %d requests in %d batches, inflight peak %d" % (
+            mode, st["completed"], st["batches"], st["inflight_peak"]))
+        assert srv.stats()["budget_in_use"] == 0
+
+
+def test_replay_poisson_stream(torch_dev):
+    torch = torch_dev
+    from paper_cs_0406049_amd import serve, workloads
+    rs = workloads.request_stream(count=2000, seed=4, pool_elems=1 << 24)
+    pool = torch.from_numpy(rs.pool).cuda()
+    sizes = np.minimum(rs.sizes, 1 << 20)
+    offs = np.minimum(rs.offsets, pool.numel() - sizes)
+    offs -= offs % 64
+    assert np.all(offs >= 0) and np.all(offs + sizes <= pool.numel())
+    xs = [pool.data_ptr() + 4 * int(o) for o in offs]
+    rate = 1e5                                   # requests per second
+    arr = (np.cumsum(rs.unit_gaps) / rate * 1e9).astype(np.int64)
+    with serve.Server(max_inflight=4, auto_release=True) as srv:
+        comp = srv.replay(xs, sizes, arr)
+        st = srv.stats()
+    assert np.all(comp["status"] == 0)
+    summ = serve.latency_summary(comp)
+    log("replay: %s, batches %d, inflight peak %d" % (summ, st["batches"], st["inflight_peak"]))
+    assert st["batches"] < comp.size
+    assert summ["p99_us"] > 0

@@ -175,3 +175,18 @@ def test_latency_summary():
     s = serve.latency_summary(comp)
     assert s["p50_us"] == pytest.approx(2.5) and s["max_us"] == pytest.approx(4.0)
     assert s["elements"] == 40 and s["span_s"] == pytest.approx(4.03e-6)
+
+
+def test_autotune_cache_keys_and_candidates(tmp_path):
+    from paper_cs_0406049_amd import autotune
+    k1 = autotune.cache_key("gfx950", 256, 4096, 453_000_000, 0, 0)
+    k2 = autotune.cache_key("gfx950", 256, 4000, 300_000_000, 0, 0)
+    k3 = autotune.cache_key("gfx950", 256, 4096, 453_000_000, 1, 0)
+    assert k1 == k2 and k1 != k3
+    cands = list(autotune.candidates(256))
+    assert len(cands) == len(autotune.BLOCKS) * len(autotune.UNROLLS) * len(autotune.WAVES_PER_CU)
+    assert all(b % 64 == 0 and u in (1, 2, 4, 8) and g >= 1 for b, u, g in cands)
+    p = str(tmp_path / "t.json")
+    autotune.save_cache({k1: {"shape": [256, 4, 2048]}}, p)
+    assert autotune.load_cache(p)[k1]["shape"] == [256, 4, 2048]
+    assert autotune.load_cache(str(tmp_path / "missing.json")) == {}
