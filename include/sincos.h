@@ -85,9 +85,10 @@ typedef enum {
 } sincos_method_t;
 
 /* Launch shape (0 in a field = library default).
- * block:  threads per workgroup, a multiple of 64 in [64, 1024].
- * unroll: float4 per thread per loop trip (1, 2, 4 or 8).
- * grid:   workgroups; 0 = enough to cover the array once (capped). */
+ * block:  threads per workgroup, a multiple of 64 in [64, 1024]; default 512.
+ * unroll: float4 per thread per loop trip (1, 2, 4 or 8); default 1.
+ * grid:   workgroups; 0 = one per tile, covering the array once (grid-stride
+ *         beyond 2^20 workgroups); for the ragged form 0 = one per unit. */
 typedef struct {
     int32_t block;
     int32_t unroll;

@@ -210,19 +210,26 @@ def sincos_copy_ceiling_f32(x, s, c, n=None, launch=None, stream=None) -> None:
 
 
 def _seg_tables(segs, lens):
+    """Segment and length tables as contiguous arrays (no per-segment ctypes
+    objects, so large batches marshal quickly)."""
+    import numpy as np
     count = len(segs)
-    st = (Seg * max(count, 1))()
-    lt = (_I64 * max(count, 1))()
-    for j, (x, s, c) in enumerate(segs):
-        st[j] = Seg(_ptr(x), _ptr(s), _ptr(c))
-        lt[j] = int(lens[j]) if lens is not None else int(x.numel())
-    return st, lt, count
+    tab = np.zeros((max(count, 1), 3), np.uint64)
+    if count:
+        tab[:count] = [[_ptr(x) or 0, _ptr(s) or 0, _ptr(c) or 0] for x, s, c in segs]
+    if lens is None:
+        lt = np.array([int(x.numel()) for x, _, _ in segs] or [0], np.int64)
+    else:
+        lt = np.ascontiguousarray(lens, np.int64) if count else np.zeros(1, np.int64)
+    st = tab.ctypes.data_as(ctypes.POINTER(Seg))
+    lp = lt.ctypes.data_as(ctypes.POINTER(_I64))
+    return (st, tab), (lp, lt), count
 
 
 def sincos_f32_ragged(segs, lens=None, stream=None, arith=ARITH_FUSED, method=METHOD_NORMALIZED,
                       launch=None) -> None:
     """segs: sequence of (x, s, c); lens: lengths (default: x.numel())."""
-    st, lt, count = _seg_tables(segs, lens)
+    (st, _keep1), (lt, _keep2), count = _seg_tables(segs, lens)
     _check(lib().sincos_f32_ragged_ex(st, lt, count, int(arith), int(method), _launch(launch),
                                       _stream(stream)))
 
@@ -233,7 +240,7 @@ class RaggedPlan:
 
     def __init__(self, segs, lens=None, arith=ARITH_FUSED, method=METHOD_NORMALIZED,
                  launch=None):
-        st, lt, count = _seg_tables(segs, lens)
+        (st, _keep1), (lt, _keep2), count = _seg_tables(segs, lens)
         h = _P()
         _check(lib().sincos_ragged_plan_create(st, lt, count, int(arith), int(method),
                                                _launch(launch), ctypes.byref(h)))

@@ -21,9 +21,12 @@ from . import _capi
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mi355_sincos", "tune.json")
 
-BLOCKS = (256, 512, 1024)
-UNROLLS = (1, 2, 4, 8)
-WAVES_PER_CU = (4, 8, 16, 32)   # persistent grid = CUs * this / (block / 256)
+BLOCKS = (256, 512)
+UNROLLS = (1, 2, 4)
+# resident waves per CU for a persistent grid (grid = CUs * waves / (block / 64));
+# 0 = one workgroup per unit of work (no persistence)
+WAVES_PER_CU = (8, 16, 32, 64, 128, 0)
+COVER = 1 << 30  # a grid this large is capped to the number of units
 
 _lock = threading.Lock()
 
@@ -59,7 +62,7 @@ def candidates(cus: int):
     for block in BLOCKS:
         for unroll in UNROLLS:
             for wpc in WAVES_PER_CU:
-                grid = max(1, cus * wpc * 256 // block // 4)
+                grid = COVER if wpc == 0 else max(1, cus * wpc * 64 // block)
                 yield (block, unroll, grid)
 
 

@@ -108,10 +108,12 @@ LaunchShape resolve_plain_shape(const LaunchShape &req, int64_t, const DeviceInf
 LaunchShape resolve_ragged_shape(const LaunchShape &req, int64_t total_units,
                                  const DeviceInfo &dev)
 {
+    (void)dev;
     LaunchShape sh = req;
-    if (sh.grid <= 0)
-        sh.grid = std::max(1, dev.cus) * 8;  // persistent: 8 workgroups per CU
-    sh.grid = (int)std::max<int64_t>(1, std::min<int64_t>(sh.grid, std::max<int64_t>(total_units, 1)));
+    // default: one workgroup per unit of work (measured faster than a
+    // persistent grid); a requested grid is capped to the number of units
+    const int64_t cap = std::min<int64_t>(std::max<int64_t>(total_units, 1), int64_t(1) << 30);
+    sh.grid = (int)(sh.grid <= 0 ? cap : std::min<int64_t>(sh.grid, cap));
     return sh;
 }
 

@@ -250,7 +250,7 @@ __global__ void __launch_bounds__(256) k_backward_scalar(const float *s, const f
 // loads).  Only the sine of each pair is used; the cosine-only operations
 // are dropped by the compiler.
 
-constexpr int kFwdIPT = 4;
+constexpr int kFwdIPT = 8;
 
 __global__ void __launch_bounds__(256) k_sinusoid_fwd(const float *t, int64_t N,
                                                       const float *__restrict__ A,
@@ -269,6 +269,7 @@ __global__ void __launch_bounds__(256) k_sinusoid_fwd(const float *t, int64_t N,
             ti[r] = i < N ? t[i] : 0.f;
             acc[r] = 0.0f;
         }
+#pragma unroll 4
         for (int32_t k = 0; k < K; ++k) {
             const float wk = w[k], pk = phi[k], ak = A[k];
 #pragma unroll
@@ -294,10 +295,10 @@ __global__ void __launch_bounds__(256) k_sinusoid_fwd(const float *t, int64_t N,
 // (j = 0: A, 1: phi, 2: w); k_sinusoid_reduce adds each row in a fixed tree
 // order (deterministic) and applies A_k.
 
-constexpr int64_t kAdjChunk = 1024;  // samples per wave
-constexpr int kAdjWaves = 4;         // waves per block (one chunk each)
+constexpr int64_t kAdjChunk = 512;  // samples per wave
+constexpr int kAdjWaves = 16;       // waves per block (one chunk each)
 
-__global__ void __launch_bounds__(256) k_sinusoid_adj(const float *__restrict__ t,
+__global__ void __launch_bounds__(64 * kAdjWaves) k_sinusoid_adj(const float *__restrict__ t,
                                                       const float *__restrict__ g, int64_t N,
                                                       const float *__restrict__ w,
                                                       const float *__restrict__ phi, int32_t K,

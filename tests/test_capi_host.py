@@ -144,8 +144,8 @@ def test_sinusoid_validation_and_workspace(L):
     assert L.sinusoid_f32_forward(None, 0, BASE, BASE, BASE, 3, None, None) == _capi.OK
     wb = L.sinusoid_f32_backward_workspace_bytes
     assert wb(-1, 4) == -1
-    assert wb(4_194_304, 64) == 4096 * 3 * 64 * 4
-    assert wb(1025, 65) == 2 * 3 * 128 * 4
+    assert wb(4_194_304, 64) == 8192 * 3 * 64 * 4      # 512-sample chunks, 64 lanes per group
+    assert wb(1025, 65) == 3 * 3 * 128 * 4
     rc = L.sinusoid_f32_backward(BASE, BASE + 4096, 4096, BASE + 8192, BASE + 8192, BASE + 8192, 64,
                                  BASE + 9000, BASE + 10000, BASE + 11000, BASE + 20000, 16, None)
     assert rc == _capi.EINVAL and "workspace" in _capi.last_error()

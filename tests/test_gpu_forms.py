@@ -253,13 +253,16 @@ def _sinusoid_small(N, K, seed):
     return t, A, w, phi
 
 
+ADJ_CHUNK = 512   # samples per wave in the adjoint kernel
+
+
 def _adjoint_bound(N, abs_sum):
     """Rounding bound of the kernel's binary32 sums against exact sums:
-    per-wave recursive fma sums over at most 1024 samples, a strided
+    per-wave recursive fma sums over at most ADJ_CHUNK samples, a strided
     per-thread pass (at most ceil(chunks/256) terms) and an 8-level tree, plus
     the rounding of g*t and of the final A_k product."""
-    chunks = max(1, -(-N // 1024))
-    depth = min(N, 1024) + -(-chunks // 256) + 8 + 3
+    chunks = max(1, -(-N // ADJ_CHUNK))
+    depth = min(N, ADJ_CHUNK) + -(-chunks // 256) + 8 + 3
     return depth * U * abs_sum * 1.001
 
 
