@@ -25,6 +25,7 @@ import numpy as np
 
 FUSED, SPLIT = 0, 1
 METHOD1, METHOD2 = 0, 1
+VARIANT_LISTING, VARIANT_NO_FIX, VARIANT_TEXT_FIX, VARIANT_EQ2 = 0, 1, 2, 3
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sincos_oracle.c")
@@ -78,6 +79,8 @@ def lib():
             L.oracle_error_scan_reduced.argtypes = [u32, u32, u32, c_int, c_int, c_int, c_int,
                                                     dp, dp, dp, fp, fp,
                                                     ctypes.POINTER(ctypes.c_int64)]
+            L.oracle_error_scan_variant.argtypes = L.oracle_error_scan_reduced.argtypes
+            L.oracle_pair_variant.argtypes = [ctypes.c_float, c_int, c_int, c_int, fp, fp]
             L.oracle_sincos_backward_f32.argtypes = [fp, fp, fp, fp, fp, i64]
             L.oracle_sinusoid_forward_f32.argtypes = [fp, i64, fp, fp, fp, i32, fp, c_int, c_int,
                                                       c_int]
@@ -165,6 +168,31 @@ def error_scan_reduced(bits_lo: int, bits_hi: int, stride: int = 1, arith: int =
         raise ValueError("oracle_error_scan_reduced failed")
     return dict(max_vec=mv.value, rms_vec=rv.value, max_amp=ma.value, argmax_vec=av.value,
                 argmax_amp=aa.value, count=cnt.value)
+
+
+def error_scan_variant(bits_lo: int, bits_hi: int, stride: int = 1, arith: int = FUSED,
+                       method: int = METHOD1, variant: int = VARIANT_LISTING,
+                       threads: int | None = None):
+    """As error_scan_reduced, for one of the Sec. II ablations (VARIANT_*)."""
+    mv, rv, ma = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    av, aa = ctypes.c_float(), ctypes.c_float()
+    cnt = ctypes.c_int64()
+    rc = lib().oracle_error_scan_variant(bits_lo, bits_hi, stride, arith, method, variant,
+                                         threads or default_threads(), ctypes.byref(mv),
+                                         ctypes.byref(rv), ctypes.byref(ma), ctypes.byref(av),
+                                         ctypes.byref(aa), ctypes.byref(cnt))
+    if rc != 0:
+        raise ValueError("oracle_error_scan_variant failed")
+    return dict(max_vec=mv.value, rms_vec=rv.value, max_amp=ma.value, argmax_vec=av.value,
+                argmax_amp=aa.value, count=cnt.value)
+
+
+def pair_variant(q1: float, arith: int = FUSED, method: int = METHOD1,
+                 variant: int = VARIANT_LISTING):
+    s, c = ctypes.c_float(), ctypes.c_float()
+    lib().oracle_pair_variant(ctypes.c_float(q1), arith, method, variant, ctypes.byref(s),
+                              ctypes.byref(c))
+    return np.float32(s.value), np.float32(c.value)
 
 
 def sincos_backward(s, c, gs=None, gc=None):

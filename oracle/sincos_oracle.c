@@ -193,6 +193,55 @@ void oracle_pair_unfixed(float q1, int arith, int method, float *s, float *c)
 }
 
 /* ---------------------------------------------------------------------- */
+/* Ablations of Sec. II (analysis only; the method is oracle_pair_from_reduced).
+ *   ORACLE_VARIANT_LISTING    the method: fix 2 - |p2|^2 taken after doubling 1
+ *   ORACLE_VARIANT_NO_FIX     no magnitude correction
+ *   ORACLE_VARIANT_TEXT_FIX   the text's form: (3 - s^2 - c^2)/2 on the final pair
+ *   ORACLE_VARIANT_EQ2        both doublings with the rejected eq. (2),
+ *                             cos 2a = 1 - 2 sin^2 a, then the listing's fix     */
+#define ORACLE_VARIANT_LISTING 0
+#define ORACLE_VARIANT_NO_FIX 1
+#define ORACLE_VARIANT_TEXT_FIX 2
+#define ORACLE_VARIANT_EQ2 3
+
+static void double_angle_eq2(float s, float c, int arith, float *s_out, float *c_out)
+{
+    float two_s = 2.0f * s;
+    *c_out = mul_sub_from(two_s, s, 1.0f, arith); /* 1 - 2 s^2 */
+    float sc = s * c;
+    *s_out = 2.0f * sc;
+}
+
+void oracle_pair_variant(float q1, int arith, int method, int variant, float *s, float *c)
+{
+    float s1, c1, s2, c2, s3, c3;
+    oracle_quarter_series(q1, arith, method, &s1, &c1);
+    if (variant == ORACLE_VARIANT_EQ2) {
+        double_angle_eq2(s1, c1, arith, &s2, &c2);
+        float m = oracle_magnitude_factor(s2, c2, arith, method);
+        double_angle_eq2(s2, c2, arith, &s3, &c3);
+        *s = s3 * m;
+        *c = c3 * m;
+        return;
+    }
+    oracle_double_angle(s1, c1, arith, &s2, &c2);
+    oracle_double_angle(s2, c2, arith, &s3, &c3);
+    if (variant == ORACLE_VARIANT_NO_FIX) {
+        *s = s3;
+        *c = c3;
+    } else if (variant == ORACLE_VARIANT_TEXT_FIX) {
+        float h = mul_sub_from(s3, s3, mul_sub_from(c3, c3, 3.0f, arith), arith);
+        float m = 0.5f * h;
+        *s = s3 * m;
+        *c = c3 * m;
+    } else {
+        float m = oracle_magnitude_factor(s2, c2, arith, method);
+        *s = s3 * m;
+        *c = c3 * m;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
 /* Array drivers.  A plain loop over elements; with threads > 1 the array is
  * cut into contiguous chunks, each run by the same scalar loop.  Each worker
  * first installs the default floating-point environment (round to nearest,
@@ -333,7 +382,7 @@ struct err_stats {
 
 struct scan_job {
     uint32_t bits_lo, bits_hi, stride;
-    int arith, method, fixed;
+    int arith, method, variant;
     struct err_stats *per_chunk; /* one slot per chunk start */
     int64_t per;                 /* chunk length, to find the slot */
 };
@@ -348,10 +397,10 @@ static void scan_chunk(void *job, int64_t lo, int64_t hi)
         float q;
         memcpy(&q, &bits, sizeof q);
         float s, c;
-        if (j->fixed)
+        if (j->variant == ORACLE_VARIANT_LISTING)
             oracle_pair_from_reduced(q, j->arith, j->method, &s, &c);
         else
-            oracle_pair_unfixed(q, j->arith, j->method, &s, &c);
+            oracle_pair_variant(q, j->arith, j->method, j->variant, &s, &c);
         double a = two_pi * (double)q, rs, rc;
         sincos(a, &rs, &rc);
         double ds = (double)s - rs, dc = (double)c - rc;
@@ -371,8 +420,25 @@ static void scan_chunk(void *job, int64_t lo, int64_t hi)
     j->per_chunk[lo / j->per] = st;
 }
 
+int oracle_error_scan_variant(uint32_t bits_lo, uint32_t bits_hi, uint32_t stride, int arith,
+                              int method, int variant, int threads, double *out_max_vec,
+                              double *out_rms_vec, double *out_max_amp, float *out_argmax_vec,
+                              float *out_argmax_amp, int64_t *out_count);
+
+/* fixed = 1: the method; fixed = 0: without step 4. */
 int oracle_error_scan_reduced(uint32_t bits_lo, uint32_t bits_hi, uint32_t stride, int arith,
                               int method, int fixed, int threads, double *out_max_vec,
+                              double *out_rms_vec, double *out_max_amp, float *out_argmax_vec,
+                              float *out_argmax_amp, int64_t *out_count)
+{
+    return oracle_error_scan_variant(bits_lo, bits_hi, stride, arith, method,
+                                     fixed ? ORACLE_VARIANT_LISTING : ORACLE_VARIANT_NO_FIX,
+                                     threads, out_max_vec, out_rms_vec, out_max_amp,
+                                     out_argmax_vec, out_argmax_amp, out_count);
+}
+
+int oracle_error_scan_variant(uint32_t bits_lo, uint32_t bits_hi, uint32_t stride, int arith,
+                              int method, int variant, int threads, double *out_max_vec,
                               double *out_rms_vec, double *out_max_amp, float *out_argmax_vec,
                               float *out_argmax_amp, int64_t *out_count)
 {
@@ -387,7 +453,7 @@ int oracle_error_scan_reduced(uint32_t bits_lo, uint32_t bits_hi, uint32_t strid
         threads = (int)n;
     struct err_stats slots[256];
     memset(slots, 0, sizeof slots);
-    struct scan_job j = {bits_lo, bits_hi, stride, arith, method, fixed, slots,
+    struct scan_job j = {bits_lo, bits_hi, stride, arith, method, variant, slots,
                          (n + threads - 1) / threads};
     run_chunks(scan_chunk, &j, n, threads);
     struct err_stats tot = {0.0, 0.0, 0.0, 0.0f, 0.0f, 0};
