@@ -140,6 +140,25 @@ def bench_ragged(torch, reps, plain_gbs):
             "speedup_vs_per_array": round(pa_ms / g_ms, 2)}
 
 
+def bench_adjoint(torch, reps, plain_gbs):
+    """Elementwise adjoint gx = gs*c - gc*s over the roofline size: 16 bytes
+    read and 4 written per element, against the plain kernel's per-byte rate."""
+    n = 1 << 28
+    g = torch.Generator(device="cuda").manual_seed(5)
+    s_ = torch.rand(n, device="cuda", generator=g)
+    c_ = torch.rand(n, device="cuda", generator=g)
+    gs = torch.rand(n, device="cuda", generator=g)
+    gc = torch.rand(n, device="cuda", generator=g)
+    gx = torch.empty_like(s_)
+    from paper_cs_0406049_amd import _capi
+    ms, _ = time_launches(torch, lambda: _capi.sincos_f32_backward(s_, c_, gs, gc, gx, n), reps, 2)
+    gbs = 20 * n / (ms * 1e-3) / 1e9
+    return {"workload": "gx = gs*c - gc*s, %d elements, both gradients (20 B/element)" % n,
+            "kernel_ms": round(ms, 4), "GBps": round(gbs, 1),
+            "roofline_frac": round(gbs / HBM_PEAK_GBPS, 4),
+            "per_byte_vs_plain": round(gbs / plain_gbs, 4)}
+
+
 def bench_sinusoid(torch, reps):
     from paper_cs_0406049_amd import _capi, workloads
     from paper_cs_0406049_amd.autograd import sinusoid_loss_and_grads
@@ -182,6 +201,55 @@ def bench_sinusoid(torch, reps):
                          "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s (VALU lane-ops)",
                          "frac": round(ops / (tot_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4),
                          "ops_per_pair": [SINUSOID_FWD_OPS, SINUSOID_ADJ_OPS]}}
+
+
+HUYGENS_OPS = 284 / 4   # VALU instructions per (point, source) pair in the loop's ISA
+
+
+def bench_huygens(torch, reps):
+    """Huygens diffraction: 512 x 512 screen points, 64 x 64 sources; the
+    fused kernel against the plain kernel composed with torch ops (phase
+    matrix in chunks, sincos kernel, weighted sums)."""
+    import numpy as np
+    from paper_cs_0406049_amd import _capi, workloads
+    p = workloads.huygens_problem()
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()  # noqa: E731
+    xo, yo, src = d(p.xo), d(p.yo), d(p.src.reshape(-1))
+    P, S = xo.numel(), p.src.shape[0]
+    re = torch.empty_like(xo)
+    im = torch.empty_like(xo)
+    ms, _ = time_launches(torch, lambda: _capi.huygens_f32(xo, yo, src, p.k, p.L, re, im), reps, 1)
+    sx, sy, sa, sp = (src.view(S, 4)[:, i] for i in range(4))
+    chunk = 1 << 16
+    th = torch.empty(chunk, S, device="cuda")
+    ss = torch.empty_like(th)
+    cc = torch.empty_like(th)
+    k32, L32 = float(np.float32(p.k)), float(np.float32(p.L))
+
+    def composed():
+        for lo in range(0, P, chunk):
+            hi = min(P, lo + chunk)
+            dx = xo[lo:hi, None] - sx[None, :]
+            dy = yo[lo:hi, None] - sy[None, :]
+            rho2 = dx * dx + dy * dy
+            r = torch.sqrt(rho2 + L32 * L32)
+            torch.mul(rho2 / (r + L32), k32, out=th[:hi - lo])
+            th[:hi - lo] += sp[None, :]
+            _capi.sincos_f32(th, ss, cc, (hi - lo) * S)
+            w = sa[None, :] / r
+            re[lo:hi] = (w * cc[:hi - lo]).sum(1)
+            im[lo:hi] = (w * ss[:hi - lo]).sum(1)
+    c_ms, _ = time_launches(torch, composed, max(2, reps // 4), 1)
+    pairs = P * S
+    tops = pairs * HUYGENS_OPS / (ms * 1e-3) / 1e12
+    return {"workload": "Huygens point-source sum: %d screen points, %d sources (64 x 64 aperture, "
+                        "lens + seeded aberration), L = %g wavelengths" % (P, S, p.L),
+            "kernel_ms": round(ms, 4), "pairs_per_s": round(pairs / (ms * 1e-3), 1),
+            "composed_plain_kernel_plus_torch_ms": round(c_ms, 3),
+            "speedup_vs_composed": round(c_ms / ms, 2),
+            "roofline": {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                         "unit": "Tops/s (VALU lane-ops)", "frac": round(tops / VALU_PEAK_TOPS, 4),
+                         "ops_per_pair": HUYGENS_OPS}}
 
 
 def bench_serve(torch, plain_gelem_s):
@@ -229,7 +297,7 @@ def main(argv=None):
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceiling", action="store_true")
-    ap.add_argument("--forms", default="ragged,sinusoid,serve",
+    ap.add_argument("--forms", default="ragged,adjoint,sinusoid,huygens,serve",
                     help="comma list of forms to measure after the plain kernel ('' = none)")
     args = ap.parse_args(argv)
 
@@ -334,8 +402,12 @@ def main(argv=None):
         log("form: %s" % f)
         if f == "ragged":
             out["forms"]["ragged"] = bench_ragged(torch, max(5, args.steps // 4), achieved)
+        elif f == "adjoint":
+            out["forms"]["adjoint"] = bench_adjoint(torch, max(5, args.steps // 4), achieved)
         elif f == "sinusoid":
             out["forms"]["sinusoid"] = bench_sinusoid(torch, max(5, args.steps // 4))
+        elif f == "huygens":
+            out["forms"]["huygens"] = bench_huygens(torch, max(5, args.steps // 10))
         elif f == "serve":
             out["forms"]["serve"] = bench_serve(torch, value)
         torch.cuda.empty_cache()

@@ -185,6 +185,22 @@ SINCOS_API int sinusoid_f32_backward(const float *t, const float *g, int64_t N, 
                           float *gphi, void *workspace, int64_t workspace_bytes, void *stream);
 
 /* ---------------------------------------------------------------------- */
+/* Huygens' principle point-source sum (the application named in Sec. IV):
+ * the complex field at P screen points (xo_i, yo_i, L) from S point sources
+ * in the plane z = 0,
+ *     U_i = sum_j (a_j / r_ij) exp(i (k (r_ij - L) + phi_j)),
+ * r_ij the distance, obliquity factor 1, the path difference r - L formed
+ * as rho^2 / (r + L) (rho the lateral distance).  In binary32: dx, dy by
+ * subtraction, rho2 = fma(dx, dx, dy*dy), r = sqrt(rho2 + fl(L*L)),
+ * d = rho2 / (r + L), theta = fma(k, d, phi_j), the pair of theta (FUSED,
+ * NORMALIZED), w = a_j / r, re = fma(w, c, re), im = fma(w, s, im) over
+ * j = 0..S-1 in order from +0; sqrt and division correctly rounded.
+ * xo, yo, re, im: [P] device arrays; src: [S][4] = (x, y, a, phi), device,
+ * 16-byte aligned.  L > 0.  Outputs may not overlap any input.           */
+SINCOS_API int huygens_f32(const float *xo, const float *yo, int64_t P, const float *src,
+                           int32_t S, float k, float L, float *re, float *im, void *stream);
+
+/* ---------------------------------------------------------------------- */
 /* Measurement helper: the same memory traffic as the plain form (read 4 B,
  * write 8 B per element, float4 body, same launch shape) with no
  * arithmetic: s[i] = x[i], c[i] = x[i].  Gives the measured bandwidth

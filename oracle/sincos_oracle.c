@@ -578,6 +578,62 @@ int oracle_sinusoid_adjoint_f64(const float *t, const float *g, int64_t N, const
     return 0;
 }
 
+/* ---------------------------------------------------------------------- */
+/* Huygens' principle (the author's application, Sec. IV): the field at
+ * screen point i (xo_i, yo_i, L) from S point sources (xa_j, ya_j, 0) of
+ * amplitude a_j and phase phi_j,
+ *     U_i = sum_j (a_j / r_ij) exp(i (k (r_ij - L) + phi_j)),
+ * with the obliquity factor taken as 1 and the path difference r - L
+ * written as rho^2 / (r + L) so that no cancellation occurs.  In binary32,
+ * sources in order j = 0..S-1, accumulators starting at +0:
+ *     dx = xo - xa;  dy = yo - ya;  rho2 = fmaf(dx, dx, dy * dy)
+ *     r = sqrtf(rho2 + L2) with L2 = L * L;  d = rho2 / (r + L)
+ *     theta = fmaf(k, d, phi);  (s, c) = the pair of theta
+ *     w = a / r;  re = fmaf(w, c, re);  im = fmaf(w, s, im)
+ * src holds (xa, ya, a, phi) per source.                                   */
+struct huygens_job {
+    const float *xo, *yo, *src;
+    int32_t S;
+    float k, L;
+    float *re, *im;
+    int arith, method;
+};
+
+static void huygens_chunk(void *job, int64_t lo, int64_t hi)
+{
+    struct huygens_job *j = (struct huygens_job *)job;
+    const float L2 = j->L * j->L;
+    for (int64_t i = lo; i < hi; i++) {
+        float re = 0.0f, im = 0.0f;
+        for (int32_t q = 0; q < j->S; q++) {
+            const float *sq = j->src + 4 * (int64_t)q;
+            float dx = j->xo[i] - sq[0];
+            float dy = j->yo[i] - sq[1];
+            float dy2 = dy * dy;
+            float rho2 = fmaf(dx, dx, dy2);
+            float r = sqrtf(rho2 + L2);
+            float d = rho2 / (r + j->L);
+            float theta = fmaf(j->k, d, sq[3]);
+            float sv, cv;
+            oracle_sincos_pair(theta, j->arith, j->method, &sv, &cv);
+            float w = sq[2] / r;
+            re = fmaf(w, cv, re);
+            im = fmaf(w, sv, im);
+        }
+        j->re[i] = re;
+        j->im[i] = im;
+    }
+}
+
+int oracle_huygens_f32(const float *xo, const float *yo, int64_t P, const float *src, int32_t S,
+                       float k, float L, float *re, float *im, int arith, int method, int threads)
+{
+    if (P < 0 || S < 0 || (P > 0 && (!xo || !yo || !re || !im)) || (S > 0 && !src))
+        return -1;
+    struct huygens_job j = {xo, yo, src, S, k, L, re, im, arith, method};
+    return run_chunks(huygens_chunk, &j, P, threads);
+}
+
 /* Constants as the oracle rounds them, for the bit-pattern test.           */
 void oracle_constants(int method, float *out8)
 {

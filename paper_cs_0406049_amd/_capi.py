@@ -92,6 +92,8 @@ _SIGNATURES = {
     "sinusoid_f32_backward": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _P, _P, _P, _P, _I64,
                                              _P]),
     "sincos_copy_ceiling_f32": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(Launch), _P]),
+    "huygens_f32": (ctypes.c_int, [_P, _P, _I64, _P, _I32, ctypes.c_float, ctypes.c_float, _P, _P,
+                                   _P]),
     "sincos_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)]),
     "sincos_server_submit": (ctypes.c_int, [_P, _P, _I64, ctypes.c_uint64, ctypes.POINTER(_I64)]),
     "sincos_server_poll": (ctypes.c_int, [_P, ctypes.POINTER(Completion), _I32,
@@ -297,6 +299,14 @@ def sinusoid_f32_backward(t, g, A, w, phi, gA, gw, gphi, workspace, workspace_by
     _check(lib().sinusoid_f32_backward(_ptr(t), _ptr(g), N, _ptr(A), _ptr(w), _ptr(phi), K,
                                        _ptr(gA), _ptr(gw), _ptr(gphi), _raw_ptr(workspace),
                                        int(workspace_bytes), _stream(stream)))
+
+
+def huygens_f32(xo, yo, src, k, L, re, im, P=None, S=None, stream=None) -> None:
+    """src: [S, 4] float32 (x, y, amplitude, phase), 16-byte aligned."""
+    P = _numel(xo, P)
+    S = int(S if S is not None else src.numel() // 4)
+    _check(lib().huygens_f32(_ptr(xo), _ptr(yo), P, _ptr(src), S, float(k), float(L), _ptr(re),
+                             _ptr(im), _stream(stream)))
 
 
 def version() -> str:

@@ -710,6 +710,36 @@ extern "C" int sinusoid_f32_backward(const float *t, const float *g, int64_t N, 
     return e == hipSuccess ? SINCOS_OK : hip_error(e, "sinusoid_f32_backward: kernel launch");
 }
 
+extern "C" int huygens_f32(const float *xo, const float *yo, int64_t P, const float *src,
+                           int32_t S, float k, float L, float *re, float *im, void *stream)
+{
+    clear_error();
+    if (P < 0 || S < 0)
+        return set_error(SINCOS_EINVAL, "huygens_f32: P < 0 or S < 0");
+    if (P == 0)
+        return SINCOS_OK;
+    if (!xo || !yo || !re || !im || (S > 0 && !src))
+        return set_error(SINCOS_EINVAL, "huygens_f32: null pointer");
+    if (!aligned4(xo) || !aligned4(yo) || !aligned4(re) || !aligned4(im) ||
+        (S > 0 && (reinterpret_cast<uintptr_t>(src) & 15)))
+        return set_error(SINCOS_EINVAL,
+                         "huygens_f32: arrays must be 4-byte aligned, src 16-byte aligned");
+    if (!(L > 0.0f) || !(L < 1e18f))
+        return set_error(SINCOS_EINVAL, "huygens_f32: L must be positive and finite");
+    if (ranges_overlap(re, P, im, P) || ranges_overlap(re, P, xo, P) ||
+        ranges_overlap(re, P, yo, P) || ranges_overlap(im, P, xo, P) ||
+        ranges_overlap(im, P, yo, P) ||
+        (S > 0 && (ranges_overlap(re, P, src, 4 * (int64_t)S) ||
+                   ranges_overlap(im, P, src, 4 * (int64_t)S))))
+        return set_error(SINCOS_EOVERLAP, "huygens_f32: outputs overlap inputs or each other");
+    const DeviceInfo *dev;
+    int rc;
+    if ((rc = current_device(&dev)) != SINCOS_OK)
+        return rc;
+    hipError_t e = launch_huygens(xo, yo, P, src, S, k, L, re, im, (hipStream_t)stream);
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "huygens_f32: kernel launch");
+}
+
 // ---------------------------------------------------------------------------
 
 extern "C" const char *sincos_last_error(void) { return g_last_error.c_str(); }

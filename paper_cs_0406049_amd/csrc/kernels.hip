@@ -212,7 +212,7 @@ __device__ __forceinline__ float adjoint1(float s, float c, float gs, float gc)
 }
 
 template <bool GS, bool GC>
-__global__ void __launch_bounds__(256) k_backward_vec(const f4 *s, const f4 *c, const f4 *gs,
+__global__ void __launch_bounds__(512) k_backward_vec(const f4 *s, const f4 *c, const f4 *gs,
                                                       const f4 *gc, f4 *gx, int64_t n4)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -360,6 +360,60 @@ __global__ void __launch_bounds__(256) k_sinusoid_reduce(const float *partial, i
             gphi[k] = A[k] * v;
         else
             gw[k] = A[k] * v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K6: Huygens point-source sum, U_i = sum_j (a_j / r_ij) exp(i (k (r_ij - L) +
+// phi_j)), the path difference as rho^2 / (r + L).  Lane <-> screen point;
+// the source table (x, y, a, phi) is read with wave-uniform float4 scalar
+// loads; sources are summed in order with fma (so the only parallel axis is
+// the screen: one point per lane keeps the most waves resident, and the
+// unrolled source loop supplies the instruction-level parallelism).  sqrt and
+// division are IEEE (correctly rounded).
+
+constexpr int kHuyIPT = 1;
+
+__global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *yo, int64_t P,
+                                                 const f4 *__restrict__ src, int32_t S, float k,
+                                                 float L, float L2, float *re, float *im)
+{
+    const int64_t bd = blockDim.x;
+    const int64_t base = (int64_t)blockIdx.x * bd * kHuyIPT + threadIdx.x;
+    float px[kHuyIPT], py[kHuyIPT], ar[kHuyIPT], ai[kHuyIPT];
+#pragma unroll
+    for (int r = 0; r < kHuyIPT; ++r) {
+        const int64_t i = base + r * bd;
+        px[r] = i < P ? xo[i] : 0.f;
+        py[r] = i < P ? yo[i] : 0.f;
+        ar[r] = 0.0f;
+        ai[r] = 0.0f;
+    }
+#pragma unroll 4
+    for (int32_t q = 0; q < S; ++q) {
+        const f4 sq = src[q];
+#pragma unroll
+        for (int r = 0; r < kHuyIPT; ++r) {
+            const float dx = px[r] - sq.x;
+            const float dy = py[r] - sq.y;
+            const float dy2 = dy * dy;
+            const float rho2 = __builtin_fmaf(dx, dx, dy2);
+            const float rr = __builtin_sqrtf(rho2 + L2);
+            const float d = rho2 / (rr + L);
+            float sv, cv;
+            sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(k, d, sq.w), sv, cv);
+            const float w = sq.z / rr;
+            ar[r] = __builtin_fmaf(w, cv, ar[r]);
+            ai[r] = __builtin_fmaf(w, sv, ai[r]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kHuyIPT; ++r) {
+        const int64_t i = base + r * bd;
+        if (i < P) {
+            re[i] = ar[r];
+            im[i] = ai[r];
+        }
     }
 }
 
@@ -551,14 +605,15 @@ hipError_t launch_backward(const float *s, const float *c, const float *gs, cons
         return hipGetLastError();
     }
     scalar(0, head);
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((n4 + 255) / 256, 16384));
+    // one float4 per thread, one tile per workgroup (grid-stride past 2^20)
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((n4 + 511) / 512, int64_t(1) << 20));
     const f4 *sv = reinterpret_cast<const f4 *>(s + head);
     const f4 *cv = reinterpret_cast<const f4 *>(c + head);
     const f4 *gsv = gs ? reinterpret_cast<const f4 *>(gs + head) : nullptr;
     const f4 *gcv = gc ? reinterpret_cast<const f4 *>(gc + head) : nullptr;
     f4 *gxv = reinterpret_cast<f4 *>(gx + head);
 #define MI355_BWD_V(GS, GC)                                                                       \
-    hipLaunchKernelGGL((k_backward_vec<GS, GC>), dim3((unsigned)grid), dim3(256), 0, st, sv, cv, \
+    hipLaunchKernelGGL((k_backward_vec<GS, GC>), dim3((unsigned)grid), dim3(512), 0, st, sv, cv, \
                        gsv, gcv, gxv, n4)
     if (gs && gc) MI355_BWD_V(true, true);
     else if (gs) MI355_BWD_V(true, false);
@@ -576,6 +631,17 @@ hipError_t launch_sinusoid_forward(const float *t, int64_t N, const float *A, co
     const int64_t grid = std::max<int64_t>(1, (N + per_block - 1) / per_block);
     hipLaunchKernelGGL(k_sinusoid_fwd, dim3((unsigned)grid), dim3(256), 0, st, t, N, A, w, phi, K,
                        y);
+    return hipGetLastError();
+}
+
+hipError_t launch_huygens(const float *xo, const float *yo, int64_t P, const float *src,
+                          int32_t S, float k, float L, float *re, float *im, hipStream_t st)
+{
+    const int64_t per_block = 256 * kHuyIPT;
+    const int64_t grid = std::max<int64_t>(1, (P + per_block - 1) / per_block);
+    const float L2 = L * L;
+    hipLaunchKernelGGL(k_huygens, dim3((unsigned)grid), dim3(256), 0, st, xo, yo, P,
+                       reinterpret_cast<const f4 *>(src), S, k, L, L2, re, im);
     return hipGetLastError();
 }
 

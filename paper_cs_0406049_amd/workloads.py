@@ -131,3 +131,42 @@ def request_stream(count: int = 10_000, lo: float = 1e3, hi: float = 1e7, seed: 
     offsets = (rng.integers(0, np.maximum(slots, 0) + 1) * 64).astype(np.int64)
     pool = rng.uniform(-1e3, 1e3, pool_elems).astype(np.float32)
     return RequestStream(sizes, gaps, offsets, pool)
+
+
+# ---------------------------------------------------------------------------
+# Huygens diffraction (the author's application)
+
+
+@dataclass
+class HuygensProblem:
+    xo: np.ndarray    # [P] screen x (wavelengths)
+    yo: np.ndarray    # [P] screen y
+    src: np.ndarray   # [S, 4] source x, y, amplitude, phase
+    k: float          # wavenumber (2 pi: lengths in wavelengths)
+    L: float          # aperture-to-screen distance
+
+
+def huygens_problem(screen_side: int = 512, aperture_side: int = 64, seed: int = 5,
+                    D: float = 256.0, W: float = 256.0, L: float = 2.0e4,
+                    aberration: float = 0.1, lens: bool = True) -> HuygensProblem:
+    """A square aperture of side D sampled by aperture_side^2 point sources on a
+    regular grid, with seeded apodization a ~ U[0.5, 1]/S; phases of a thin lens
+    focusing on the screen centre (if lens) plus seeded aberration N(0, aberration^2);
+    a square screen of side W, screen_side^2 points, at distance L.  Lengths in
+    wavelengths (k = 2 pi).  The phases are made in binary64, then rounded."""
+    rng = np.random.default_rng(seed)
+    k = 2.0 * math.pi
+    g = (np.arange(aperture_side) + 0.5) / aperture_side * D - D / 2
+    xa, ya = np.meshgrid(g, g, indexing="xy")
+    xa, ya = xa.ravel(), ya.ravel()
+    S = xa.size
+    a = rng.uniform(0.5, 1.0, S) / S
+    phi = np.zeros(S)
+    if lens:
+        phi -= k * (np.sqrt(xa * xa + ya * ya + L * L) - L)
+    phi += aberration * rng.standard_normal(S)
+    src = np.stack([xa, ya, a, phi], axis=1).astype(np.float32)
+    h = (np.arange(screen_side) + 0.5) / screen_side * W - W / 2
+    xo, yo = np.meshgrid(h, h, indexing="xy")
+    return HuygensProblem(xo.ravel().astype(np.float32), yo.ravel().astype(np.float32),
+                          np.ascontiguousarray(src), k, L)

@@ -1,0 +1,78 @@
+"""Huygens point-source sum on the GPU: bit-exact against the oracle (the
+binary32 sequence, sources summed in order, IEEE sqrt and division)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_bit_exact, lib_loaded, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lib_loaded()
+    return torch
+
+
+def run(torch, xo, yo, src, k, L):
+    from paper_cs_0406049_amd import _capi
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()  # noqa: E731
+    xd, yd, sd = d(xo), d(yo), d(src.reshape(-1))
+    re = torch.empty_like(xd)
+    im = torch.empty_like(xd)
+    _capi.huygens_f32(xd, yd, sd, k, L, re, im, xd.numel(), src.shape[0])
+    torch.cuda.synchronize()
+    return re.cpu().numpy(), im.cpu().numpy()
+
+
+@pytest.mark.parametrize("P,S", [(1, 1), (5, 3), (4099, 1000), (1025, 4097), (3, 0)])
+def test_bit_exact_small(torch_dev, P, S):
+    rng = np.random.default_rng(P + S)
+    src = np.stack([rng.uniform(-100, 100, S), rng.uniform(-100, 100, S), rng.uniform(0, 1, S) / max(S, 1),
+                    rng.uniform(-math.pi, math.pi, S)], 1).astype(np.float32).reshape(S, 4)
+    xo = rng.uniform(-300, 300, P).astype(np.float32)
+    yo = rng.uniform(-300, 300, P).astype(np.float32)
+    re, im = run(torch_dev, xo, yo, src, 2 * math.pi, 4000.0)
+    ro, io = oracle.huygens(xo, yo, src, 2 * math.pi, 4000.0, threads=oracle.default_threads())
+    assert_bit_exact(re, ro, "re P=%d S=%d" % (P, S))
+    assert_bit_exact(im, io, "im P=%d S=%d" % (P, S))
+
+
+@pytest.mark.slow
+def test_diffraction_workload_sampled(torch_dev):
+    """512 x 512 screen, 64 x 64 sources (lens + aberration): every sampled
+    point bit-exact against the oracle."""
+    from paper_cs_0406049_amd import workloads
+    p = workloads.huygens_problem()
+    re, im = run(torch_dev, p.xo, p.yo, p.src, p.k, p.L)
+    idx = np.random.default_rng(0).choice(p.xo.size, 3000, replace=False)
+    idx = np.concatenate([idx, [0, p.xo.size - 1, p.xo.size // 2 + 256]])
+    ro, io = oracle.huygens(p.xo[idx], p.yo[idx], p.src, p.k, p.L, threads=oracle.default_threads())
+    assert_bit_exact(re[idx], ro, "re (sample)")
+    assert_bit_exact(im[idx], io, "im (sample)")
+    inten = re.astype(np.float64) ** 2 + im.astype(np.float64) ** 2
+    peak = int(np.argmax(inten))
+    log("diffraction: peak intensity %.3g at (%.1f, %.1f), centre %.3g" % (
+        inten[peak], p.xo[peak], p.yo[peak], inten[p.xo.size // 2 + 256]))
+    # the lens focuses on the screen centre
+    assert abs(p.xo[peak]) < 2.0 and abs(p.yo[peak]) < 2.0
+
+
+def test_validation(torch_dev):
+    torch = torch_dev
+    from paper_cs_0406049_amd import _capi
+    x = torch.zeros(8, device="cuda")
+    src = torch.zeros(16, device="cuda")
+    out = torch.empty(8, device="cuda")
+    out2 = torch.empty(8, device="cuda")
+    with pytest.raises(_capi.SincosError):
+        _capi.huygens_f32(x, x, src, 1.0, -1.0, out, out2)          # L <= 0
+    with pytest.raises(_capi.SincosError):
+        _capi.huygens_f32(x, x, src, 1.0, 10.0, out, out)           # re == im
+    with pytest.raises(_capi.SincosError):
+        _capi.huygens_f32(x, x, src[1:].data_ptr(), 1.0, 10.0, out, out2, 8, 3)  # src misaligned

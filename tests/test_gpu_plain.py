@@ -31,10 +31,12 @@ def run(torch, x_host, arith=FUSED, method=0, launch=None):
     return s.cpu().numpy(), c.cpu().numpy()
 
 
+@pytest.mark.parametrize("method", [0, 1])
 @pytest.mark.parametrize("arith", [FUSED, SPLIT])
 @pytest.mark.parametrize("quarter", [0, 1, 2, 3])
-def test_exhaustive_all_bit_patterns(torch_dev, arith, quarter):
-    """Every one of the 2^32 binary32 inputs, in four quarters per mode."""
+def test_exhaustive_all_bit_patterns(torch_dev, arith, quarter, method):
+    """Every one of the 2^32 binary32 inputs, in four quarters per mode and
+    method."""
     torch = torch_dev
     from paper_cs_0406049_amd import _capi
     chunk = 1 << 26
@@ -47,12 +49,12 @@ def test_exhaustive_all_bit_patterns(torch_dev, arith, quarter):
         lo = lo_q + k * chunk
         xb = np.arange(lo, lo + chunk, dtype=np.uint64).astype(np.uint32).view(np.float32)
         xs.copy_(torch.from_numpy(xb))
-        _capi.sincos_f32_ex(xs, s, c, chunk, arith, 0)
+        _capi.sincos_f32_ex(xs, s, c, chunk, arith, method)
         sg, cg = s.cpu().numpy(), c.cpu().numpy()
-        so, co = oracle.sincos(xb, arith, 0, threads=threads)
+        so, co = oracle.sincos(xb, arith, method, threads=threads)
         assert_bit_exact(sg, so, "sin bits %08x.." % lo, xb)
         assert_bit_exact(cg, co, "cos bits %08x.." % lo, xb)
-    log("exhaustive arith=%d quarter=%d: 2^30 inputs bit-exact" % (arith, quarter))
+    log("exhaustive arith=%d method=%d quarter=%d: 2^30 inputs bit-exact" % (arith, method, quarter))
 
 
 @pytest.mark.parametrize("arith", [FUSED, SPLIT])

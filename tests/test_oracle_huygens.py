@@ -1,0 +1,119 @@
+"""Pins of the oracle's Huygens point-source sum: a single source in closed
+form, the exact double-precision model within a derived bound, the
+Fraunhofer (far-field) limit of a square aperture, and symmetry."""
+import math
+
+import numpy as np
+
+import oracle
+
+U = 2.0 ** -24
+K = 2.0 * math.pi
+
+
+def exact_field(xo, yo, src, k, L):
+    """U_i = sum_j a_j / r exp(i (k (r - L) + phi_j)) in double precision on the
+    same binary32 inputs."""
+    xo = xo.astype(np.float64)[:, None]
+    yo = yo.astype(np.float64)[:, None]
+    xa, ya, a, phi = (src[:, i].astype(np.float64)[None, :] for i in range(4))
+    rho2 = (xo - xa) ** 2 + (yo - ya) ** 2
+    r = np.sqrt(rho2 + float(L) ** 2)
+    d = rho2 / (r + float(L))
+    theta = float(np.float32(k)) * d + phi
+    w = a / r
+    return (w * np.cos(theta)).sum(1), (w * np.sin(theta)).sum(1), w, theta, d
+
+
+def field_bound(w, theta, d, k):
+    """Per-point bound on |U32 - U64|: each term's pair error E_pair(theta)
+    plus its phase error (d is formed with about 8 roundings, theta with one
+    more), the rounding of w, and the recursive fma sum over S terms."""
+    x1 = np.abs(theta) / (2 * math.pi)
+    e_pair = 4.95e-7 + np.abs(theta) * 4.1e-8 + math.pi * np.maximum(x1, 1e-30) * 2 * U
+    e_phase = abs(k) * 8 * U * d + 2 * U * np.abs(theta)
+    S = w.shape[1]
+    return (w * (e_pair + e_phase + 3 * U)).sum(1) + 2 * S * U * w.sum(1)
+
+
+def test_single_source_closed_form(orc):
+    xo = np.array([0.0, 3.0, -7.5, 20.0], np.float32)
+    yo = np.array([0.0, 4.0, 2.25, -9.0], np.float32)
+    src = np.array([[1.0, -2.0, 0.75, 0.3]], np.float32)
+    L = 1000.0
+    re, im = orc.huygens(xo, yo, src, K, L)
+    er, ei, w, th, d = exact_field(xo, yo, src, K, L)
+    b = field_bound(w, th, d, K)
+    assert np.all(np.hypot(re - er, im - ei) <= b)
+    # on the source's axis the path difference is 0: U = a/L e^{i phi}
+    re0, im0 = orc.huygens(np.array([1.0], np.float32), np.array([-2.0], np.float32), src, K, L)
+    assert abs(re0[0] - 0.75 / L * math.cos(0.3)) < 2e-7 * 0.75 / L * 10
+    assert abs(im0[0] - 0.75 / L * math.sin(0.3)) < 2e-7 * 0.75 / L * 10
+
+
+def test_against_exact_model_within_bound(orc):
+    rng = np.random.default_rng(6)
+    S, P = 300, 500
+    src = np.stack([rng.uniform(-50, 50, S), rng.uniform(-50, 50, S), rng.uniform(0, 1, S) / S,
+                    rng.uniform(-3, 3, S)], 1).astype(np.float32)
+    xo = rng.uniform(-200, 200, P).astype(np.float32)
+    yo = rng.uniform(-200, 200, P).astype(np.float32)
+    L = 5000.0
+    re, im = orc.huygens(xo, yo, src, K, L, threads=4)
+    er, ei, w, th, d = exact_field(xo, yo, src, K, L)
+    err = np.hypot(re - er, im - ei)
+    b = field_bound(w, th, d, K)
+    assert np.all(err <= b), (err / b).max()
+    # and the bound is not vacuous: the field itself is far larger
+    assert np.median(b) < 1e-3 * np.median(np.hypot(er, ei)) * 10
+
+
+def test_fraunhofer_limit_of_a_square_aperture(orc):
+    """Plane wave, M x M sources of pitch p, far screen: |U| = |D_M(u) D_M(v)| / L
+    with D_M(u) = sin(M u/2) / (M sin(u/2)), u = k p x / L (the Dirichlet
+    kernel, the sampled aperture's far-field pattern)."""
+    M, p, L = 32, 1.0, 1.0e5
+    g = (np.arange(M) - (M - 1) / 2) * p
+    xa, ya = np.meshgrid(g, g)
+    S = M * M
+    src = np.stack([xa.ravel(), ya.ravel(), np.full(S, 1.0 / S), np.zeros(S)], 1).astype(np.float32)
+    xs = np.array([0.0, 150.0, 400.0, 700.0, 1200.0, 2100.0], np.float32)
+    xo = np.concatenate([xs, xs]).astype(np.float32)
+    yo = np.concatenate([np.zeros_like(xs), xs]).astype(np.float32)
+    re, im = orc.huygens(xo, yo, src, K, L, threads=4)
+    amp = np.hypot(re, im) * L
+
+    def dirichlet(u):
+        u = np.asarray(u, np.float64)
+        out = np.ones_like(u)
+        nz = np.abs(np.sin(u / 2)) > 1e-12
+        out[nz] = np.sin(M * u[nz] / 2) / (M * np.sin(u[nz] / 2))
+        return np.abs(out)
+    ux = K * p * xo.astype(np.float64) / L
+    uy = K * p * yo.astype(np.float64) / L
+    want = dirichlet(ux) * dirichlet(uy)
+    assert abs(amp[0] - 1.0) < 1e-3                 # on axis: all sources in phase
+    assert np.all(np.abs(amp - want) < 0.01), np.c_[amp, want]
+
+
+def test_mirror_symmetry(orc):
+    M = 16
+    g = (np.arange(M) - (M - 1) / 2) * 3.0
+    xa, ya = np.meshgrid(g, g)
+    S = M * M
+    src = np.stack([xa.ravel(), ya.ravel(), np.full(S, 1.0 / S), np.zeros(S)], 1).astype(np.float32)
+    x = np.linspace(0, 300, 37).astype(np.float32)
+    y = np.linspace(-100, 200, 37).astype(np.float32)
+    L = 3000.0
+    r1, i1 = orc.huygens(x, y, src, K, L)
+    r2, i2 = orc.huygens(-x, y, src, K, L)
+    r3, i3 = orc.huygens(y, x, src, K, L)
+    tol = 64 * U * np.abs(src[:, 2]).sum() / L * 10
+    assert np.all(np.hypot(r1 - r2, i1 - i2) < tol)
+    assert np.all(np.hypot(r1 - r3, i1 - i3) < tol)
+
+
+def test_no_sources_gives_zero(orc):
+    re, im = orc.huygens(np.zeros(3, np.float32), np.zeros(3, np.float32),
+                         np.zeros((0, 4), np.float32), K, 10.0)
+    assert np.all(re == 0) and np.all(im == 0) and not np.any(np.signbit(re))

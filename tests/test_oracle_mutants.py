@@ -151,3 +151,49 @@ def test_mutant_fails_a_pin(tmp_path, name):
     assert old in src, "mutation site not found: " + name
     L = _build(tmp_path, name, src.replace(old, new, 1))
     assert failed_pins(L), "no pin caught mutant " + name
+
+
+# ---------------------------------------------------------------------------
+# The Huygens sum's pins catch plausible mistakes in it too.
+
+HUYGENS_MUTANTS = {
+    "amp_times_r": ("float w = sq[2] / r;", "float w = sq[2] * r;"),
+    "drop_dy": ("float rho2 = fmaf(dx, dx, dy2);", "float rho2 = dx * dx; (void)dy2;"),
+    "path_minus_L": ("float d = rho2 / (r + j->L);", "float d = r - j->L;"),
+    "path_no_L": ("float d = rho2 / (r + j->L);", "float d = rho2 / r;"),
+    "phase_sign": ("float theta = fmaf(j->k, d, sq[3]);", "float theta = fmaf(j->k, d, -sq[3]);"),
+    "swap_re_im": ("re = fmaf(w, cv, re);\n            im = fmaf(w, sv, im);",
+                   "re = fmaf(w, sv, re);\n            im = fmaf(w, cv, im);"),
+    "L2_missing": ("float r = sqrtf(rho2 + L2);", "float r = sqrtf(rho2 + j->L);"),
+}
+
+
+def huygens_pins_fail(L):
+    import math
+    from test_oracle_huygens import K, exact_field, field_bound
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.oracle_huygens_f32.argtypes = [fp, fp, ctypes.c_int64, fp, ctypes.c_int32, ctypes.c_float,
+                                     ctypes.c_float, fp, fp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    rng = np.random.default_rng(6)
+    S, P = 200, 300
+    src = np.stack([rng.uniform(-50, 50, S), rng.uniform(-50, 50, S), rng.uniform(0, 1, S) / S,
+                    rng.uniform(-3, 3, S)], 1).astype(np.float32)
+    xo = rng.uniform(-200, 200, P).astype(np.float32)
+    yo = rng.uniform(-200, 200, P).astype(np.float32)
+    re, im = np.empty(P, np.float32), np.empty(P, np.float32)
+    L.oracle_huygens_f32(_p(xo), _p(yo), P, _p(np.ascontiguousarray(src)), S, K, 5000.0,
+                         _p(re), _p(im), 0, 0, 2)
+    er, ei, w, th, d = exact_field(xo, yo, src, K, 5000.0)
+    return not np.all(np.hypot(re - er, im - ei) <= field_bound(w, th, d, K))
+
+
+def test_unmodified_huygens_passes(tmp_path):
+    assert not huygens_pins_fail(_build(tmp_path, "hclean", open(SRC).read()))
+
+
+@pytest.mark.parametrize("name", sorted(HUYGENS_MUTANTS))
+def test_huygens_mutant_fails_a_pin(tmp_path, name):
+    src = open(SRC).read()
+    old, new = HUYGENS_MUTANTS[name]
+    assert old in src, "mutation site not found: " + name
+    assert huygens_pins_fail(_build(tmp_path, name, src.replace(old, new, 1))), name
