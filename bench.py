@@ -203,6 +203,24 @@ def bench_sinusoid(torch, reps):
                          "ops_per_pair": [SINUSOID_FWD_OPS, SINUSOID_ADJ_OPS]}}
 
 
+def bench_interleaved(torch, reps, plain_gbs, x_host):
+    """complex64 (cos, sin) output over the roofline workload: the same 12
+    bytes per element in one interleaved stream."""
+    from paper_cs_0406049_amd import _capi
+    n = x_host.size
+    x = torch.from_numpy(x_host).cuda()
+    out = torch.empty(2 * n, device="cuda")
+    res = {}
+    for layout, name in ((0, "complex64"), (1, "phase_blocks")):
+        ms, _ = time_launches(torch, lambda: _capi.sincos_f32_interleaved(x, out, n, layout), reps, 2)
+        gbs = BYTES_PER_ELEM * n / (ms * 1e-3) / 1e9
+        res[name] = {"kernel_ms": round(ms, 4), "GBps": round(gbs, 1),
+                     "roofline_frac": round(gbs / HBM_PEAK_GBPS, 4),
+                     "per_byte_vs_plain": round(gbs / plain_gbs, 4)}
+    res["workload"] = "the roofline workload (%d angles) written as one interleaved array" % n
+    return res
+
+
 HUYGENS_OPS = 284 / 4   # VALU instructions per (point, source) pair in the loop's ISA
 
 
@@ -297,7 +315,7 @@ def main(argv=None):
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceiling", action="store_true")
-    ap.add_argument("--forms", default="ragged,adjoint,sinusoid,huygens,serve",
+    ap.add_argument("--forms", default="ragged,interleaved,adjoint,sinusoid,huygens,serve",
                     help="comma list of forms to measure after the plain kernel ('' = none)")
     args = ap.parse_args(argv)
 
@@ -402,6 +420,9 @@ def main(argv=None):
         log("form: %s" % f)
         if f == "ragged":
             out["forms"]["ragged"] = bench_ragged(torch, max(5, args.steps // 4), achieved)
+        elif f == "interleaved":
+            out["forms"]["interleaved"] = bench_interleaved(torch, max(5, args.steps // 4),
+                                                            achieved, x_host)
         elif f == "adjoint":
             out["forms"]["adjoint"] = bench_adjoint(torch, max(5, args.steps // 4), achieved)
         elif f == "sinusoid":

@@ -106,6 +106,18 @@ SINCOS_API int sincos_f32(const float *x, float *s, float *c, int64_t n, void *s
 SINCOS_API int sincos_f32_ex(const float *x, float *s, float *c, int64_t n, int32_t arith, int32_t method,
                   const sincos_launch_t *launch, void *stream);
 
+/* Interleaved outputs: the same pairs (FUSED, NORMALIZED) written to one
+ * array.
+ *   layout 0: complex64 e^{ix}: out[2i] = cos x_i, out[2i+1] = sin x_i
+ *             (out holds 2 n floats);
+ *   layout 1: the phase blocks of the paper's sample implementation: for each
+ *             4 consecutive elements, 4 sines then 4 cosines (out holds
+ *             8 ceil(n/4) floats; a final partial block leaves its unused slots
+ *             untouched).
+ * x and out 16-byte aligned, no overlap between them.                     */
+SINCOS_API int sincos_f32_interleaved(const float *x, float *out, int64_t n, int32_t layout,
+                                      void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Ragged form: `count` independent arrays in ONE persistent kernel launch.
  * segs[j] = {x_j, s_j, c_j} (device pointers), lens[j] >= 0 its length.

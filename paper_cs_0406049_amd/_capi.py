@@ -92,6 +92,7 @@ _SIGNATURES = {
     "sinusoid_f32_backward": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _P, _P, _P, _P, _I64,
                                              _P]),
     "sincos_copy_ceiling_f32": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(Launch), _P]),
+    "sincos_f32_interleaved": (ctypes.c_int, [_P, _P, _I64, _I32, _P]),
     "huygens_f32": (ctypes.c_int, [_P, _P, _I64, _P, _I32, ctypes.c_float, ctypes.c_float, _P, _P,
                                    _P]),
     "sincos_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)]),
@@ -204,6 +205,12 @@ def sincos_f32_ex(x, s, c, n=None, arith=ARITH_FUSED, method=METHOD_NORMALIZED, 
                   stream=None) -> None:
     _check(lib().sincos_f32_ex(_ptr(x), _ptr(s), _ptr(c), _numel(x, n), int(arith), int(method),
                                _launch(launch), _stream(stream)))
+
+
+def sincos_f32_interleaved(x, out, n=None, layout=0, stream=None) -> None:
+    """layout 0: complex64 (cos, sin) pairs; 1: blocks of 4 sines, 4 cosines."""
+    _check(lib().sincos_f32_interleaved(_ptr(x), _raw_ptr(out), _numel(x, n), int(layout),
+                                        _stream(stream)))
 
 
 def sincos_copy_ceiling_f32(x, s, c, n=None, launch=None, stream=None) -> None:

@@ -398,6 +398,34 @@ extern "C" int sincos_f32(const float *x, float *s, float *c, int64_t n, void *s
                          stream);
 }
 
+extern "C" int sincos_f32_interleaved(const float *x, float *out, int64_t n, int32_t layout,
+                                      void *stream)
+{
+    clear_error();
+    if (n < 0)
+        return set_error(SINCOS_EINVAL, "sincos_f32_interleaved: n < 0");
+    if (layout != 0 && layout != 1)
+        return set_error(SINCOS_EINVAL, "sincos_f32_interleaved: layout must be 0 or 1");
+    if (n == 0)
+        return SINCOS_OK;
+    if (!x || !out)
+        return set_error(SINCOS_EINVAL, "sincos_f32_interleaved: null pointer with n > 0");
+    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(out)) & 15)
+        return set_error(SINCOS_EINVAL, "sincos_f32_interleaved: x and out must be 16-byte aligned");
+    if (n > (int64_t(1) << 60))
+        return set_error(SINCOS_EINVAL, "sincos_f32_interleaved: n too large");
+    // out holds 2n floats (layout 1 rounds the last block up to 8 floats)
+    const int64_t out_floats = layout == 0 ? 2 * n : 8 * ((n + 3) / 4);
+    if (ranges_overlap(x, n, out, out_floats))
+        return set_error(SINCOS_EOVERLAP, "sincos_f32_interleaved: x overlaps out");
+    const DeviceInfo *dev;
+    int rc;
+    if ((rc = current_device(&dev)) != SINCOS_OK)
+        return rc;
+    hipError_t e = launch_sincos_interleaved(x, out, n, layout, (hipStream_t)stream);
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "sincos_f32_interleaved: kernel launch");
+}
+
 extern "C" int sincos_copy_ceiling_f32(const float *x, float *s, float *c, int64_t n,
                                        const sincos_launch_t *launch, void *stream)
 {

@@ -42,6 +42,8 @@ const DeviceInfo &device_info(int device);
 // ---- launchers (kernels.hip); each returns the hipError_t of the launch ----
 hipError_t launch_sincos(const float *x, float *s, float *c, int64_t n, int arith, int method,
                          const LaunchShape &shape, hipStream_t stream);
+hipError_t launch_sincos_interleaved(const float *x, float *out, int64_t n, int layout,
+                                     hipStream_t stream);
 hipError_t launch_copy_ceiling(const float *x, float *s, float *c, int64_t n,
                                const LaunchShape &shape, hipStream_t stream);
 hipError_t launch_ragged(const RaggedDesc *desc, const int64_t *ubeg, int32_t count,

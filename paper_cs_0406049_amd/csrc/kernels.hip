@@ -113,6 +113,67 @@ __global__ void __launch_bounds__(1024) k_sincos_vec(const float *x, float *s, f
         stream_vec_tile<A, M, U>(xv, sv, cv, base, n4, bd);
 }
 
+// K1b: interleaved outputs.  Each lane computes 4 consecutive pairs; their 8
+// output floats go to LDS at the lane's own 32-byte slot, in the chosen
+// order, and the wave then stores its 2 KB as two fully contiguous float4
+// rows (lane l writes float4 l and 64 + l of the wave's region) instead of
+// two half-filled rows.
+//   LAYOUT 0: complex64 e^{ix}: out[2i] = cos x_i, out[2i + 1] = sin x_i
+//   LAYOUT 1: the paper's phase blocks: per 4 elements, 4 sines then 4 cosines
+// x and out 16-byte aligned; n4 = n / 4 whole blocks (the caller does the
+// tail).  Block size is fixed at 256 (4 waves).
+
+template <int LAYOUT>
+__global__ void __launch_bounds__(256) k_sincos_interleaved(const f4 *x, f4 *out, int64_t n4)
+{
+    __shared__ f4 stage[4][128];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t wbase = (int64_t)blockIdx.x * 256 + wave * 64;  // first float4 of x for this wave
+    if (wbase >= n4)
+        return;  // whole wave past the end (wave-uniform)
+    f4 so = f4{0.f, 0.f, 0.f, 0.f}, co = so;
+    if (i < n4)
+        pair4<Arith::Fused, Method::Normalized>(__builtin_nontemporal_load(x + i), so, co);
+    if (LAYOUT == 0) {
+        stage[wave][2 * lane] = f4{co.x, so.x, co.y, so.y};
+        stage[wave][2 * lane + 1] = f4{co.z, so.z, co.w, so.w};
+    } else {
+        stage[wave][2 * lane] = so;
+        stage[wave][2 * lane + 1] = co;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int64_t valid = min<int64_t>(64, n4 - wbase);  // float4 of x this wave covers
+    f4 *dst = out + 2 * wbase;
+    if (lane < 2 * valid)
+        __builtin_nontemporal_store(stage[wave][lane], dst + lane);
+    if (64 + lane < 2 * valid)
+        __builtin_nontemporal_store(stage[wave][64 + lane], dst + 64 + lane);
+}
+
+// The last n % 4 elements of an interleaved output (complex layout: pair i at
+// out[2i], out[2i+1]; block layout: a final partial block of 4 sines then 4
+// cosines, its unused slots untouched).
+__global__ void __launch_bounds__(64) k_interleaved_tail(const float *x, float *out, int64_t lo,
+                                                         int64_t n, int layout)
+{
+    const int64_t i = lo + threadIdx.x;
+    if (i >= n)
+        return;
+    float sv, cv;
+    sincos_pair<Arith::Fused, Method::Normalized>(x[i], sv, cv);
+    if (layout == 0) {
+        out[2 * i] = cv;
+        out[2 * i + 1] = sv;
+    } else {
+        out[2 * lo + (i - lo)] = sv;
+        out[2 * lo + 4 + (i - lo)] = cv;
+    }
+}
+
 // x, s, c with different offsets modulo 16 bytes: scalar stream.
 template <Arith A, Method M, int U>
 __global__ void __launch_bounds__(1024) k_sincos_scalar(const float *x, float *s, float *c,
@@ -504,6 +565,30 @@ hipError_t launch_sincos(const float *x, float *s, float *c, int64_t n, int arit
         return m2 ? launch_plain_am<Arith::Fused, Method::Arctan>(x, s, c, n, sh, st)
                   : launch_plain_am<Arith::Fused, Method::Normalized>(x, s, c, n, sh, st);
     }
+}
+
+hipError_t launch_sincos_interleaved(const float *x, float *out, int64_t n, int layout,
+                                     hipStream_t st)
+{
+    const int64_t n4 = n / 4;
+    if (n4 > 0) {
+        const int64_t grid = (n4 + 255) / 256;
+        if (layout == 0)
+            hipLaunchKernelGGL(k_sincos_interleaved<0>, dim3((unsigned)grid), dim3(256), 0, st,
+                               reinterpret_cast<const f4 *>(x), reinterpret_cast<f4 *>(out), n4);
+        else
+            hipLaunchKernelGGL(k_sincos_interleaved<1>, dim3((unsigned)grid), dim3(256), 0, st,
+                               reinterpret_cast<const f4 *>(x), reinterpret_cast<f4 *>(out), n4);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    const int64_t rem = n - 4 * n4;
+    if (rem > 0) {
+        hipLaunchKernelGGL(k_interleaved_tail, dim3(1), dim3(64), 0, st, x, out, n4 * 4, n, layout);
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_copy_ceiling(const float *x, float *s, float *c, int64_t n,

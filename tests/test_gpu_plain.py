@@ -202,3 +202,35 @@ def test_gpu_accuracy_matches_paper(torch_dev):
     rms = float(np.sqrt(np.mean(e ** 2)))
     log("GPU RMS vector error %.3g (paper 1.2e-7), max %.3g" % (rms, e.max()))
     assert abs(rms / 1.2e-7 - 1) < 0.05
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+def test_interleaved_layouts(torch_dev, layout):
+    """complex64 (cos, sin) pairs, and the paper's blocks of 4 sines then 4
+    cosines: the same bits as the SoA pairs, nothing written past the end."""
+    torch = torch_dev
+    from paper_cs_0406049_amd import _capi
+    rng = np.random.default_rng(30 + layout)
+    for n in list(range(0, 21)) + [255, 256, 257, 1023, 1_000_003, 1 << 22]:
+        xh = rng.uniform(-1e3, 1e3, n).astype(np.float32)
+        so, co = oracle.sincos(xh, FUSED, 0, threads=oracle.default_threads())
+        out_len = 2 * n if layout == 0 else 8 * ((n + 3) // 4)
+        x = torch.from_numpy(xh).cuda() if n else torch.empty(0, device="cuda")
+        out = torch.from_numpy(np.full(out_len + 64, CANARY, np.uint32).view(np.float32)).cuda()
+        _capi.sincos_f32_interleaved(x, out, n, layout)
+        torch.cuda.synchronize()
+        oh = out.cpu().numpy()
+        if layout == 0:
+            assert_bit_exact(oh[0:2 * n:2], co, "cos n=%d" % n, xh)
+            assert_bit_exact(oh[1:2 * n:2], so, "sin n=%d" % n, xh)
+        else:
+            nb = (n + 3) // 4
+            blocks = oh[:8 * nb].reshape(nb, 8) if nb else np.zeros((0, 8), np.float32)
+            sp = np.full(4 * nb, np.nan, np.float32)
+            cp = np.full(4 * nb, np.nan, np.float32)
+            sp[:n], cp[:n] = so, co
+            for b in range(nb):
+                m = min(4, n - 4 * b)
+                assert np.array_equal(blocks[b, :m].view(np.uint32), sp[4 * b:4 * b + m].view(np.uint32)), (n, b)
+                assert np.array_equal(blocks[b, 4:4 + m].view(np.uint32), cp[4 * b:4 * b + m].view(np.uint32)), (n, b)
+        assert np.all(oh[out_len:].view(np.uint32) == CANARY), n
