@@ -32,8 +32,10 @@ HBM_PEAK_GBPS = 8000.0
 BYTES_PER_ELEM = 12
 METRIC = "sincos Gelem/s & % HBM roofline (fp32, 1 GPU); p50/p99 latency served"
 PMC_FILE = os.path.join(ROOT, "profiles", "plain_sincos_268M_pmc.json")
+# what determines the plain kernel's code and launch: its arithmetic, the
+# streaming helpers, its source and launcher, and the default launch shape
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_cs_0406049_amd", "csrc", f)
-                  for f in ("kernels.hip", "sincos_core.hpp", "internal.hpp", "capi.cpp")]
+                  for f in ("sincos_core.hpp", "stream.hpp", "plain.hip", "internal.hpp")]
 CEILING_SHAPES = ((64, 1, 0), (256, 1, 0), (512, 1, 0))
 
 

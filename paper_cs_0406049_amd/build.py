@@ -14,8 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmi355_sincos.so")
 
-SOURCES = ["kernels.hip", "capi.cpp", "serve.cpp"]
-HEADERS = ["internal.hpp", "sincos_core.hpp", "serve.hpp"]
+SOURCES = ["plain.hip", "forms.hip", "capi.cpp", "serve.cpp"]
+HEADERS = ["internal.hpp", "sincos_core.hpp", "stream.hpp", "serve.hpp"]
 
 # -ffp-contract=off: the SPLIT arithmetic must not be fused (FUSED uses
 # explicit fma builtins, CONTRACT re-enables contraction with a pragma).

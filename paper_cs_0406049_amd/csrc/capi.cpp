@@ -97,14 +97,6 @@ static int check_shape(const sincos_launch_t *req, LaunchShape *out)
     return SINCOS_OK;
 }
 
-LaunchShape resolve_plain_shape(const LaunchShape &req, int64_t, const DeviceInfo &)
-{
-    LaunchShape sh = req;
-    if (sh.grid <= 0 || sh.grid > (1 << 20))
-        sh.grid = 1 << 20;  // cover the array (grid-stride beyond this)
-    return sh;
-}
-
 LaunchShape resolve_ragged_shape(const LaunchShape &req, int64_t total_units,
                                  const DeviceInfo &dev)
 {

@@ -1,118 +1,14 @@
-// kernels.hip -- gfx950 kernels of the sine-cosine library and their launchers.
-//
-// Every kernel is elementwise over binary32 VALU arithmetic (sincos_core.hpp);
-// the plain and ragged forms are bound by HBM traffic (4 bytes read, 8 bytes
-// written per element), so the kernels are written for streaming: float4
-// (16-byte) loads and stores per lane, several float4 in flight per lane,
-// non-temporal hints (the data is touched once and is far larger than the
-// caches), and 64-bit indexing throughout.
+// forms.hip -- the kernels built around the plain form's arithmetic: the
+// interleaved-output, ragged, adjoint, sinusoid-model and Huygens kernels and
+// their launchers.  All arithmetic is binary32 VALU (sincos_core.hpp).
 #include "internal.hpp"
-#include "sincos_core.hpp"
+#include "stream.hpp"
 
 #include <algorithm>
 
 namespace mi355 {
 
-typedef float f4 __attribute__((ext_vector_type(4)));
-
 // ---------------------------------------------------------------------------
-// Small device helpers.
-
-template <Arith A, Method M>
-__device__ __forceinline__ void pair4(const f4 v, f4 &so, f4 &co)
-{
-    float s0, s1, s2, s3, c0, c1, c2, c3;
-    sincos_pair<A, M>(v.x, s0, c0);
-    sincos_pair<A, M>(v.y, s1, c1);
-    sincos_pair<A, M>(v.z, s2, c2);
-    sincos_pair<A, M>(v.w, s3, c3);
-    so = f4{s0, s1, s2, s3};
-    co = f4{c0, c1, c2, c3};
-}
-
-template <Arith A, Method M>
-__device__ __forceinline__ void pair1_store(const float *x, float *s, float *c, int64_t i)
-{
-    float so, co;
-    sincos_pair<A, M>(x[i], so, co);
-    s[i] = so;
-    c[i] = co;
-}
-
-// One block's share of a float4 stream: U float4 per lane, lanes strided by
-// the block size so that each of the U loads is one coalesced row.
-template <Arith A, Method M, int U>
-__device__ __forceinline__ void stream_vec_tile(const f4 *xv, f4 *sv, f4 *cv, int64_t base,
-                                                int64_t n4, int64_t bd)
-{
-    f4 v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int64_t j = base + u * bd;
-        v[u] = j < n4 ? __builtin_nontemporal_load(xv + j) : f4{0.f, 0.f, 0.f, 0.f};
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int64_t j = base + u * bd;
-        if (j < n4) {
-            f4 so, co;
-            pair4<A, M>(v[u], so, co);
-            __builtin_nontemporal_store(so, sv + j);
-            __builtin_nontemporal_store(co, cv + j);
-        }
-    }
-}
-
-// Scalar version: U*4 elements per lane per trip.
-template <Arith A, Method M, int U>
-__device__ __forceinline__ void stream_scalar_tile(const float *x, float *s, float *c,
-                                                   int64_t base, int64_t n, int64_t bd)
-{
-    constexpr int R = 4 * U;
-    float v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t j = base + r * bd;
-        v[r] = j < n ? __builtin_nontemporal_load(x + j) : 0.f;
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t j = base + r * bd;
-        if (j < n) {
-            float so, co;
-            sincos_pair<A, M>(v[r], so, co);
-            __builtin_nontemporal_store(so, s + j);
-            __builtin_nontemporal_store(co, c + j);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// K1: plain form.  x, s, c share their offset modulo 16 bytes; `head` scalar
-// elements precede the 16-byte aligned float4 body of n4 vectors and `tail`
-// scalar elements follow it.  Block 0 also does the <= 6 scalar elements.
-
-template <Arith A, Method M, int U>
-__global__ void __launch_bounds__(1024) k_sincos_vec(const float *x, float *s, float *c,
-                                                     int64_t n4, int head, int tail)
-{
-    if (blockIdx.x == 0) {
-        const int t = threadIdx.x;
-        if (t < head) {
-            pair1_store<A, M>(x, s, c, t);
-        } else if (t >= 4 && t < 4 + tail) {
-            pair1_store<A, M>(x, s, c, head + 4 * n4 + (t - 4));
-        }
-    }
-    const f4 *xv = reinterpret_cast<const f4 *>(x + head);
-    f4 *sv = reinterpret_cast<f4 *>(s + head);
-    f4 *cv = reinterpret_cast<f4 *>(c + head);
-    const int64_t bd = blockDim.x;
-    const int64_t stride = (int64_t)gridDim.x * bd * U;
-    for (int64_t base = (int64_t)blockIdx.x * bd * U + threadIdx.x; base < n4; base += stride)
-        stream_vec_tile<A, M, U>(xv, sv, cv, base, n4, bd);
-}
-
 // K1b: interleaved outputs.  Each lane computes 4 consecutive pairs; their 8
 // output floats go to LDS at the lane's own 32-byte slot, in the chosen
 // order, and the wave then stores its 2 KB as two fully contiguous float4
@@ -171,41 +67,6 @@ __global__ void __launch_bounds__(64) k_interleaved_tail(const float *x, float *
     } else {
         out[2 * lo + (i - lo)] = sv;
         out[2 * lo + 4 + (i - lo)] = cv;
-    }
-}
-
-// x, s, c with different offsets modulo 16 bytes: scalar stream.
-template <Arith A, Method M, int U>
-__global__ void __launch_bounds__(1024) k_sincos_scalar(const float *x, float *s, float *c,
-                                                        int64_t n)
-{
-    const int64_t bd = blockDim.x;
-    const int64_t stride = (int64_t)gridDim.x * bd * U * 4;
-    for (int64_t base = (int64_t)blockIdx.x * bd * U * 4 + threadIdx.x; base < n; base += stride)
-        stream_scalar_tile<A, M, U>(x, s, c, base, n, bd);
-}
-
-// Bandwidth ceiling: the plain kernel's traffic with no arithmetic.
-template <int U>
-__global__ void __launch_bounds__(1024) k_copy_1r2w(const f4 *x, f4 *s, f4 *c, int64_t n4)
-{
-    const int64_t bd = blockDim.x;
-    const int64_t stride = (int64_t)gridDim.x * bd * U;
-    for (int64_t base = (int64_t)blockIdx.x * bd * U + threadIdx.x; base < n4; base += stride) {
-        f4 v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t j = base + u * bd;
-            v[u] = j < n4 ? __builtin_nontemporal_load(x + j) : f4{0.f, 0.f, 0.f, 0.f};
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t j = base + u * bd;
-            if (j < n4) {
-                __builtin_nontemporal_store(v[u], s + j);
-                __builtin_nontemporal_store(v[u], c + j);
-            }
-        }
     }
 }
 
@@ -484,52 +345,6 @@ __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *y
 namespace {
 
 template <Arith A, Method M>
-hipError_t launch_plain_am(const float *x, float *s, float *c, int64_t n,
-                           const LaunchShape &sh, hipStream_t st)
-{
-    const uintptr_t ax = reinterpret_cast<uintptr_t>(x), as = reinterpret_cast<uintptr_t>(s),
-                    ac = reinterpret_cast<uintptr_t>(c);
-    const bool same_phase = (ax & 15) == (as & 15) && (ax & 15) == (ac & 15);
-    const int64_t head = same_phase ? (int64_t)(((16 - (ax & 15)) & 15) >> 2) : 0;
-    if (!same_phase || n < head + 4) {
-        const int64_t per_block = (int64_t)sh.block * sh.unroll * 4;
-        int64_t grid = (n + per_block - 1) / per_block;
-        if (sh.grid > 0)
-            grid = std::min<int64_t>(grid, sh.grid);
-        grid = std::max<int64_t>(grid, 1);
-#define MI355_SCALAR(UU)                                                                       \
-    hipLaunchKernelGGL((k_sincos_scalar<A, M, UU>), dim3((unsigned)grid), dim3(sh.block), 0, st, \
-                       x, s, c, n)
-        switch (sh.unroll) {
-        case 1: MI355_SCALAR(1); break;
-        case 2: MI355_SCALAR(2); break;
-        case 8: MI355_SCALAR(8); break;
-        default: MI355_SCALAR(4); break;
-        }
-#undef MI355_SCALAR
-        return hipGetLastError();
-    }
-    const int64_t n4 = (n - head) / 4;
-    const int tail = (int)(n - head - 4 * n4);
-    const int64_t per_block = (int64_t)sh.block * sh.unroll;
-    int64_t grid = (n4 + per_block - 1) / per_block;
-    if (sh.grid > 0)
-        grid = std::min<int64_t>(grid, sh.grid);
-    grid = std::max<int64_t>(grid, 1);
-#define MI355_VEC(UU)                                                                        \
-    hipLaunchKernelGGL((k_sincos_vec<A, M, UU>), dim3((unsigned)grid), dim3(sh.block), 0, st, \
-                       x, s, c, n4, (int)head, tail)
-    switch (sh.unroll) {
-    case 1: MI355_VEC(1); break;
-    case 2: MI355_VEC(2); break;
-    case 8: MI355_VEC(8); break;
-    default: MI355_VEC(4); break;
-    }
-#undef MI355_VEC
-    return hipGetLastError();
-}
-
-template <Arith A, Method M>
 hipError_t launch_ragged_am(const RaggedDesc *desc, const int64_t *ubeg, int32_t count,
                             int64_t total_units, const LaunchShape &sh, hipStream_t st)
 {
@@ -549,23 +364,6 @@ hipError_t launch_ragged_am(const RaggedDesc *desc, const int64_t *ubeg, int32_t
 }
 
 }  // namespace
-
-hipError_t launch_sincos(const float *x, float *s, float *c, int64_t n, int arith, int method,
-                         const LaunchShape &sh, hipStream_t st)
-{
-    const bool m2 = method == (int)Method::Arctan;
-    switch (arith) {
-    case (int)Arith::Split:
-        return m2 ? launch_plain_am<Arith::Split, Method::Arctan>(x, s, c, n, sh, st)
-                  : launch_plain_am<Arith::Split, Method::Normalized>(x, s, c, n, sh, st);
-    case (int)Arith::Contract:
-        return m2 ? launch_plain_am<Arith::Contract, Method::Arctan>(x, s, c, n, sh, st)
-                  : launch_plain_am<Arith::Contract, Method::Normalized>(x, s, c, n, sh, st);
-    default:
-        return m2 ? launch_plain_am<Arith::Fused, Method::Arctan>(x, s, c, n, sh, st)
-                  : launch_plain_am<Arith::Fused, Method::Normalized>(x, s, c, n, sh, st);
-    }
-}
 
 hipError_t launch_sincos_interleaved(const float *x, float *out, int64_t n, int layout,
                                      hipStream_t st)
@@ -589,31 +387,6 @@ hipError_t launch_sincos_interleaved(const float *x, float *out, int64_t n, int 
         return hipGetLastError();
     }
     return hipSuccess;
-}
-
-hipError_t launch_copy_ceiling(const float *x, float *s, float *c, int64_t n,
-                               const LaunchShape &sh, hipStream_t st)
-{
-    const int64_t n4 = n / 4;  // caller guarantees 16-byte alignment and n % 4 == 0
-    const int64_t per_block = (int64_t)sh.block * sh.unroll;
-    int64_t grid = (n4 + per_block - 1) / per_block;
-    if (sh.grid > 0)
-        grid = std::min<int64_t>(grid, sh.grid);
-    grid = std::max<int64_t>(grid, 1);
-    const f4 *xv = reinterpret_cast<const f4 *>(x);
-    f4 *sv = reinterpret_cast<f4 *>(s);
-    f4 *cv = reinterpret_cast<f4 *>(c);
-#define MI355_COPY(UU)                                                                     \
-    hipLaunchKernelGGL((k_copy_1r2w<UU>), dim3((unsigned)grid), dim3(sh.block), 0, st, xv, sv, \
-                       cv, n4)
-    switch (sh.unroll) {
-    case 1: MI355_COPY(1); break;
-    case 2: MI355_COPY(2); break;
-    case 8: MI355_COPY(8); break;
-    default: MI355_COPY(4); break;
-    }
-#undef MI355_COPY
-    return hipGetLastError();
 }
 
 hipError_t launch_ragged(const RaggedDesc *desc, const int64_t *ubeg, int32_t count,

@@ -39,7 +39,7 @@ struct DeviceInfo {
 };
 const DeviceInfo &device_info(int device);
 
-// ---- launchers (kernels.hip); each returns the hipError_t of the launch ----
+// ---- launchers (plain.hip, forms.hip); each returns the hipError_t of the launch ----
 hipError_t launch_sincos(const float *x, float *s, float *c, int64_t n, int arith, int method,
                          const LaunchShape &shape, hipStream_t stream);
 hipError_t launch_sincos_interleaved(const float *x, float *out, int64_t n, int layout,

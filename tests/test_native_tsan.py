@@ -21,7 +21,7 @@ def test_server_under_thread_sanitizer(tmp_path):
     cmd = [hipcc, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-ffp-contract=off",
            "-Xarch_host", "-fsanitize=thread",
            "-I", os.path.join(ROOT, "include"),
-           os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "capi.cpp"),
+           os.path.join(CSRC, "plain.hip"), os.path.join(CSRC, "forms.hip"), os.path.join(CSRC, "capi.cpp"),
            os.path.join(CSRC, "serve.cpp"), os.path.join(ROOT, "tests", "native", "serve_stress.cpp"),
            "-o", str(exe), "-lpthread"]
     subprocess.check_call(cmd, stderr=subprocess.DEVNULL)
