@@ -92,11 +92,17 @@ def cpu_baseline(x_host, arith: int):
     t0 = time.perf_counter()
     oracle.sincos(x_host, arith, 0, threads=threads)
     dt = time.perf_counter() - t0
+    m = 1 << 25   # single-thread leg: the first 32 Mi elements
+    t0 = time.perf_counter()
+    oracle.sincos(x_host[:m], arith, 0, threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": x_host.size / dt / 1e9, "unit": "Gelem/s", "cores": threads,
             "kind": "oracle",
             "sample": "the full %d-element array, one pass, %s arithmetic, %d threads over "
-                      "contiguous chunks (%.2f s wall)" % (x_host.size, ["fused", "split"][arith],
-                                                           threads, dt)}
+                      "contiguous chunks (%.2f s wall); single thread on its first %d elements: "
+                      "%.4f Gelem/s" % (x_host.size, ["fused", "split"][arith], threads, dt, m,
+                                        m / dt1 / 1e9),
+            "single_thread_value": round(m / dt1 / 1e9, 5)}
 
 
 # ---------------------------------------------------------------------------
