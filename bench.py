@@ -404,7 +404,7 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": wl, "n": n, "bytes_per_elem": BYTES_PER_ELEM,
                    "arith": args.arith, "method": "normalized (first method)",
-                   "launch": {"block": args.block or 512, "unroll": args.unroll or 1,
+                   "launch": {"block": args.block or 256, "unroll": args.unroll or 1,
                               "grid": args.grid or "one workgroup per tile"},
                    "device": props.name, "cus": props.multi_processor_count},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,

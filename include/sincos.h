@@ -85,7 +85,7 @@ typedef enum {
 } sincos_method_t;
 
 /* Launch shape (0 in a field = library default).
- * block:  threads per workgroup, a multiple of 64 in [64, 1024]; default 512.
+ * block:  threads per workgroup, a multiple of 64 in [64, 1024]; default 256.
  * unroll: float4 per thread per loop trip (1, 2, 4 or 8); default 1.
  * grid:   workgroups; 0 = one per tile, covering the array once (grid-stride
  *         beyond 2^20 workgroups); for the ragged form 0 = one per unit. */

@@ -22,10 +22,10 @@ struct RaggedDesc {
 };
 static_assert(sizeof(RaggedDesc) == 48, "descriptor layout");
 
-// Default: 512 threads, one float4 per thread, one tile per workgroup (the
+// Default: 256 threads, one float4 per thread, one tile per workgroup (the
 // fastest measured shape for the 1-read / 2-write stream on MI355X).
 struct LaunchShape {
-    int block = 512;
+    int block = 256;
     int unroll = 1;
     int grid = 0;
 };

@@ -3,8 +3,8 @@
 //
 // The plain form is bound by HBM traffic (4 bytes read, 8 bytes written per
 // element), so the kernel streams: one float4 load and two float4 stores per
-// lane, non-temporal hints (the data is touched once and is far larger than
-// the caches), one tile per workgroup, 64-bit indexing.
+// lane as buffer instructions with explicit cache policy (non-temporal loads,
+// sc1 stores), one tile per workgroup, a buffer resource per tile.
 #include "internal.hpp"
 #include "stream.hpp"
 
@@ -32,10 +32,10 @@ __global__ void __launch_bounds__(1024) k_sincos_vec(const float *x, float *s, f
     const f4 *xv = reinterpret_cast<const f4 *>(x + head);
     f4 *sv = reinterpret_cast<f4 *>(s + head);
     f4 *cv = reinterpret_cast<f4 *>(c + head);
-    const int64_t bd = blockDim.x;
-    const int64_t stride = (int64_t)gridDim.x * bd * U;
-    for (int64_t base = (int64_t)blockIdx.x * bd * U + threadIdx.x; base < n4; base += stride)
-        stream_vec_tile<A, M, U>(xv, sv, cv, base, n4, bd);
+    const int bd = blockDim.x;
+    const int64_t tile = (int64_t)bd * U;
+    for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < n4; t0 += (int64_t)gridDim.x * tile)
+        buffer_vec_tile<A, M, U>(xv, sv, cv, t0, n4, bd);
 }
 
 // x, s, c with different offsets modulo 16 bytes: scalar stream.
@@ -49,26 +49,28 @@ __global__ void __launch_bounds__(1024) k_sincos_scalar(const float *x, float *s
         stream_scalar_tile<A, M, U>(x, s, c, base, n, bd);
 }
 
-// Bandwidth ceiling: the plain kernel's traffic with no arithmetic.
+// Bandwidth ceiling: the plain kernel's traffic, instructions and cache
+// policy with no arithmetic (s = c = x).
 template <int U>
 __global__ void __launch_bounds__(1024) k_copy_1r2w(const f4 *x, f4 *s, f4 *c, int64_t n4)
 {
-    const int64_t bd = blockDim.x;
-    const int64_t stride = (int64_t)gridDim.x * bd * U;
-    for (int64_t base = (int64_t)blockIdx.x * bd * U + threadIdx.x; base < n4; base += stride) {
-        f4 v[U];
+    const int bd = blockDim.x;
+    const int64_t tile = (int64_t)bd * U;
+    for (int64_t t0 = (int64_t)blockIdx.x * tile; t0 < n4; t0 += (int64_t)gridDim.x * tile) {
+        const int64_t bytes = min<int64_t>(tile, n4 - t0) * 16;
+        const __amdgpu_buffer_rsrc_t rx = tile_rsrc(x + t0, bytes);
+        const __amdgpu_buffer_rsrc_t rs = tile_rsrc(s + t0, bytes);
+        const __amdgpu_buffer_rsrc_t rc = tile_rsrc(c + t0, bytes);
+        u4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            v[u] = __builtin_amdgcn_raw_buffer_load_b128(rx, (int)(threadIdx.x + u * bd) * 16, 0,
+                                                         kLoadPolicy);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t j = base + u * bd;
-            v[u] = j < n4 ? __builtin_nontemporal_load(x + j) : f4{0.f, 0.f, 0.f, 0.f};
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t j = base + u * bd;
-            if (j < n4) {
-                __builtin_nontemporal_store(v[u], s + j);
-                __builtin_nontemporal_store(v[u], c + j);
-            }
+            const int off = (int)(threadIdx.x + u * bd) * 16;
+            __builtin_amdgcn_raw_buffer_store_b128(v[u], rs, off, 0, kStorePolicy);
+            __builtin_amdgcn_raw_buffer_store_b128(v[u], rc, off, 0, kStorePolicy);
         }
     }
 }
