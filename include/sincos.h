@@ -297,6 +297,27 @@ SINCOS_API int sincos_server_replay(sincos_server_t *srv, const float *const *xs
 SINCOS_API int sincos_server_destroy(sincos_server_t *srv);
 
 /* ---------------------------------------------------------------------- */
+/* Process-wide default launch shapes: the autotuner's hook.  The shape of a
+ * call that passes no launch shape (and the fields it leaves 0) comes from
+ * here: sincos_f32, sincos_f32_ex and sincos_copy_ceiling_f32 take "plain";
+ * sincos_f32_ragged(_ex), ragged plans and the server's batches take
+ * "ragged" (the server's one-launch-per-request mode takes "plain").
+ * json: a JSON object {"plain": {...}, "ragged": {...}}, each holding any of
+ *       the integer fields "block", "unroll", "grid" with the meanings and
+ *       limits of sincos_launch_t.  Forms and fields left out get the
+ *       built-in defaults (256, 1, 0), so NULL or "{}" restores them.
+ * Errors: EINVAL for text outside that form (unknown keys, non-integers,
+ * trailing text) or values out of range; the current shapes are then kept.
+ * Thread-safe.  Takes effect for calls that start after it returns; plans
+ * keep the shape they were created with.  No GPU is needed.              */
+SINCOS_API int sincos_set_tuning(const char *json);
+
+/* The shapes in effect, written as the JSON object sincos_set_tuning takes.
+ * Writes at most cap - 1 characters and a terminating NUL into buf (buf may
+ * be NULL when cap is 0); returns the full length of the text.            */
+SINCOS_API int64_t sincos_get_tuning(char *buf, int64_t cap);
+
+/* ---------------------------------------------------------------------- */
 /* Message for the last non-OK status returned on this thread ("" if none). */
 SINCOS_API const char *sincos_last_error(void);
 

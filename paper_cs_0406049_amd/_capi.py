@@ -10,6 +10,7 @@ there is no fallback path.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 import threading
 
@@ -105,6 +106,8 @@ _SIGNATURES = {
                                             ctypes.POINTER(_I64), _I32,
                                             ctypes.POINTER(Completion)]),
     "sincos_server_destroy": (ctypes.c_int, [_P]),
+    "sincos_set_tuning": (ctypes.c_int, [ctypes.c_char_p]),
+    "sincos_get_tuning": (ctypes.c_int64, [ctypes.c_char_p, _I64]),
     "sincos_last_error": (ctypes.c_char_p, []),
     "sincos_version": (ctypes.c_char_p, []),
 }
@@ -314,6 +317,30 @@ def huygens_f32(xo, yo, src, k, L, re, im, P=None, S=None, stream=None) -> None:
     S = int(S if S is not None else src.numel() // 4)
     _check(lib().huygens_f32(_ptr(xo), _ptr(yo), P, _ptr(src), S, float(k), float(L), _ptr(re),
                              _ptr(im), _stream(stream)))
+
+
+def set_tuning(shapes) -> None:
+    """Install process-wide default launch shapes.  shapes: None (built-in
+    defaults) or {"plain": {...}, "ragged": {...}} with any of the integer
+    fields "block", "unroll", "grid"; a (block, unroll, grid) tuple may stand
+    for a form's dict."""
+    if shapes is None:
+        _check(lib().sincos_set_tuning(None))
+        return
+    doc = {}
+    for form, sh in shapes.items():
+        if isinstance(sh, (tuple, list)):
+            sh = dict(zip(("block", "unroll", "grid"), sh))
+        doc[form] = {k: int(v) for k, v in sh.items()}
+    _check(lib().sincos_set_tuning(json.dumps(doc).encode()))
+
+
+def get_tuning() -> dict:
+    """The default launch shapes in effect, as {"plain": {...}, "ragged": {...}}."""
+    n = lib().sincos_get_tuning(None, 0)
+    buf = ctypes.create_string_buffer(int(n) + 1)
+    lib().sincos_get_tuning(buf, n + 1)
+    return json.loads(buf.value.decode())
 
 
 def version() -> str:

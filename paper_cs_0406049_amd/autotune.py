@@ -9,6 +9,9 @@ similar size reuses it without timing.
 
     shape = autotune.tune_ragged(segs, lens)        # (block, unroll, grid)
     plan = _capi.RaggedPlan(segs, lens, launch=shape)
+
+or, with install_default=True, the choice becomes the library's process-wide default
+for ragged calls that pass no launch shape (sincos_set_tuning).
 """
 from __future__ import annotations
 
@@ -81,11 +84,31 @@ def time_plan(torch, plan, reps: int = 5) -> float:
     return a.elapsed_time(b) / reps
 
 
+def install(form: str, shape) -> None:
+    """Make shape = (block, unroll, grid) the library's default launch shape
+    for form ("plain" or "ragged"), keeping the other form's default."""
+    if form not in ("plain", "ragged"):
+        raise ValueError("form must be 'plain' or 'ragged'")
+    cur = _capi.get_tuning()
+    cur[form] = dict(zip(("block", "unroll", "grid"), (int(v) for v in shape)))
+    _capi.set_tuning(cur)
+
+
 def tune_ragged(segs, lens=None, arith: int = _capi.ARITH_FUSED,
                 method: int = _capi.METHOD_NORMALIZED, cache_path: str | None = DEFAULT_CACHE,
-                force: bool = False, reps: int = 5, verbose: bool = False):
+                force: bool = False, reps: int = 5, verbose: bool = False,
+                install_default: bool = False):
     """Best (block, unroll, grid) for this batch (from the cache if present).
-    The arrays' contents are overwritten with valid outputs while timing."""
+    The arrays' contents are overwritten with valid outputs while timing.
+    With install_default, the choice also becomes the library's default for
+    ragged calls (grid capped there to each call's units)."""
+    best = _tune_ragged(segs, lens, arith, method, cache_path, force, reps, verbose)
+    if install_default:
+        install("ragged", best)
+    return best
+
+
+def _tune_ragged(segs, lens, arith, method, cache_path, force, reps, verbose):
     import torch
     props = torch.cuda.get_device_properties(torch.cuda.current_device())
     arch = getattr(props, "gcnArchName", "unknown").split(":")[0]

@@ -77,24 +77,22 @@ static int current_device(const DeviceInfo **out)
 // ---------------------------------------------------------------------------
 // Launch shapes
 
-static int check_shape(const sincos_launch_t *req, LaunchShape *out)
+// A caller's shape over the form's current default (0 in a field = default).
+static int check_shape(const sincos_launch_t *req, int form, LaunchShape *out)
 {
-    LaunchShape sh;
+    LaunchShape sh = default_shape(form);
     if (req) {
         if (req->block != 0)
             sh.block = req->block;
         if (req->unroll != 0)
             sh.unroll = req->unroll;
-        sh.grid = req->grid;
+        if (req->grid != 0)
+            sh.grid = req->grid;
     }
-    if (sh.block < 64 || sh.block > 1024 || sh.block % 64 != 0)
-        return set_error(SINCOS_EINVAL, "launch.block must be a multiple of 64 in [64, 1024]");
-    if (sh.unroll != 1 && sh.unroll != 2 && sh.unroll != 4 && sh.unroll != 8)
-        return set_error(SINCOS_EINVAL, "launch.unroll must be 1, 2, 4 or 8");
-    if (sh.grid < 0)
-        return set_error(SINCOS_EINVAL, "launch.grid must be >= 0");
-    *out = sh;
-    return SINCOS_OK;
+    const int rc = validate_shape(sh, "launch");
+    if (rc == SINCOS_OK)
+        *out = sh;
+    return rc;
 }
 
 LaunchShape resolve_ragged_shape(const LaunchShape &req, int64_t total_units,
@@ -372,7 +370,7 @@ extern "C" int sincos_f32_ex(const float *x, float *s, float *c, int64_t n, int3
     if ((rc = check_modes(arith, method)) != SINCOS_OK)
         return rc;
     LaunchShape sh;
-    if ((rc = check_shape(launch, &sh)) != SINCOS_OK)
+    if ((rc = check_shape(launch, kFormPlain, &sh)) != SINCOS_OK)
         return rc;
     if (n == 0)
         return SINCOS_OK;
@@ -433,7 +431,7 @@ extern "C" int sincos_copy_ceiling_f32(const float *x, float *s, float *c, int64
         return set_error(SINCOS_EINVAL,
                          "sincos_copy_ceiling_f32: needs 16-byte aligned arrays and n % 4 == 0");
     LaunchShape sh;
-    if ((rc = check_shape(launch, &sh)) != SINCOS_OK)
+    if ((rc = check_shape(launch, kFormPlain, &sh)) != SINCOS_OK)
         return rc;
     if (n == 0)
         return SINCOS_OK;
@@ -459,7 +457,7 @@ extern "C" int sincos_f32_ragged_ex(const sincos_seg_t *segs, const int64_t *len
     if ((rc = check_modes(arith, method)) != SINCOS_OK)
         return rc;
     LaunchShape sh;
-    if ((rc = check_shape(launch, &sh)) != SINCOS_OK)
+    if ((rc = check_shape(launch, kFormRagged, &sh)) != SINCOS_OK)
         return rc;
     if (count == 0)
         return SINCOS_OK;
@@ -513,7 +511,7 @@ extern "C" int sincos_ragged_plan_create(const sincos_seg_t *segs, const int64_t
     if ((rc = check_modes(arith, method)) != SINCOS_OK)
         return rc;
     LaunchShape sh;
-    if ((rc = check_shape(launch, &sh)) != SINCOS_OK)
+    if ((rc = check_shape(launch, kFormRagged, &sh)) != SINCOS_OK)
         return rc;
     const DeviceInfo *dev;
     if ((rc = current_device(&dev)) != SINCOS_OK)

@@ -30,6 +30,11 @@ struct LaunchShape {
     int grid = 0;
 };
 
+// Process-wide defaults per form, installed by sincos_set_tuning.
+enum { kFormPlain = 0, kFormRagged = 1 };
+LaunchShape default_shape(int form);
+int validate_shape(const LaunchShape &sh, const char *who);
+
 // Device facts the launchers need (cached per device).
 struct DeviceInfo {
     int device = -1;

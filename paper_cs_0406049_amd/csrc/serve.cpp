@@ -109,7 +109,7 @@ public:
     int launch(int slot, const std::vector<Request *> &batch) override
     {
         Slot &sl = slots_[slot];
-        LaunchShape shape;
+        const LaunchShape shape = default_shape(mode_ == 1 ? kFormPlain : kFormRagged);
         int rc = SINCOS_OK;
         if (mode_ == 1) {
             for (Request *r : batch) {

@@ -164,3 +164,36 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(_capi, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         _capi.lib()
+
+
+def test_tuning_round_trip_and_rejection(L):
+    from paper_cs_0406049_amd import autotune
+    builtin = {"plain": {"block": 256, "unroll": 1, "grid": 0},
+               "ragged": {"block": 256, "unroll": 1, "grid": 0}}
+    try:
+        _capi.set_tuning(None)
+        assert _capi.get_tuning() == builtin
+        autotune.install("ragged", (512, 2, 4096))
+        want = {"plain": builtin["plain"], "ragged": {"block": 512, "unroll": 2, "grid": 4096}}
+        assert _capi.get_tuning() == want
+        # a form left out of the text gets the built-in shape back
+        _capi.set_tuning({"plain": {"unroll": 4}})
+        assert _capi.get_tuning() == {"plain": {"block": 256, "unroll": 4, "grid": 0},
+                                      "ragged": builtin["ragged"]}
+        _capi.set_tuning({"plain": (512, 2, 0), "ragged": (1024, 8, 7)})
+        kept = _capi.get_tuning()
+        for bad in (b'{"plain": {"block": 100}}', b'{"plain": {"unroll": 3}}',
+                    b'{"ragged": {"grid": -1}}', b'{"plan": {}}', b'{"plain": {"block": 1.5}}',
+                    b'{"plain": {"block": 256', b'{} x', b'[]', b'{"plain": {"warps": 4}}',
+                    b'{"plain": {"block": 99999999999}}', b''):
+            assert L.sincos_set_tuning(bad) == _capi.EINVAL, bad
+            assert "sincos_set_tuning" in _capi.last_error()
+            assert _capi.get_tuning() == kept, bad
+        # a short buffer is truncated with a terminator; the return is the full length
+        n = L.sincos_get_tuning(None, 0)
+        buf = ctypes.create_string_buffer(16)
+        assert L.sincos_get_tuning(buf, 16) == n and len(buf.value) == 15
+        assert L.sincos_set_tuning(b" { } ") == _capi.OK
+        assert _capi.get_tuning() == builtin
+    finally:
+        _capi.set_tuning(None)

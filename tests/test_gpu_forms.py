@@ -55,6 +55,33 @@ def test_ragged_mixed_lengths(torch_dev, launch):
     _check_segments(xs_h, segs, "ragged %r" % (launch,))
 
 
+def test_tuned_default_shapes_apply_and_keep_bits(torch_dev):
+    """Shapes installed with sincos_set_tuning are used by calls that pass
+    none (a ragged plan reports them) and leave every output bit unchanged."""
+    torch = torch_dev
+    from paper_cs_0406049_amd import _capi
+    lens = [0, 1, 5, 17, 1023, 4097, 100000, 3]
+    try:
+        _capi.set_tuning({"plain": (512, 4, 7), "ragged": (128, 2, 9)})
+        xs_h, segs = _segments(torch, lens, 11)
+        _capi.sincos_f32_ragged(segs, lens)
+        torch.cuda.synchronize()
+        _check_segments(xs_h, segs, "ragged, tuned default")
+        plan = _capi.RaggedPlan(segs, lens)
+        i = plan.info()
+        assert (i["block"], i["unroll"], i["grid"]) == (128, 2, 9)
+        plan.destroy()
+        x = torch.from_numpy(xs_h[6]).cuda()
+        s, c = torch.empty_like(x), torch.empty_like(x)
+        _capi.sincos_f32(x, s, c)
+        torch.cuda.synchronize()
+        so, co = oracle.sincos(xs_h[6], 0, 0)
+        assert_bit_exact(s.cpu().numpy(), so, "plain, tuned default sin", xs_h[6])
+        assert_bit_exact(c.cpu().numpy(), co, "plain, tuned default cos", xs_h[6])
+    finally:
+        _capi.set_tuning(None)
+
+
 @pytest.mark.parametrize("arith", [0, 1])
 def test_ragged_equals_per_array_plain(torch_dev, arith):
     """The ragged launch gives, per element, the same bits as one plain launch

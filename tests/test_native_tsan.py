@@ -8,8 +8,9 @@ import subprocess
 
 import pytest
 
+from paper_cs_0406049_amd import build as hipbuild
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-CSRC = os.path.join(ROOT, "paper_cs_0406049_amd", "csrc")
 
 
 @pytest.mark.slow
@@ -21,8 +22,7 @@ def test_server_under_thread_sanitizer(tmp_path):
     cmd = [hipcc, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-ffp-contract=off",
            "-Xarch_host", "-fsanitize=thread",
            "-I", os.path.join(ROOT, "include"),
-           os.path.join(CSRC, "plain.hip"), os.path.join(CSRC, "forms.hip"), os.path.join(CSRC, "capi.cpp"),
-           os.path.join(CSRC, "serve.cpp"), os.path.join(ROOT, "tests", "native", "serve_stress.cpp"),
+           *hipbuild.sources(), os.path.join(ROOT, "tests", "native", "serve_stress.cpp"),
            "-o", str(exe), "-lpthread"]
     subprocess.check_call(cmd, stderr=subprocess.DEVNULL)
     env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 second_deadlock_stack=1")
