@@ -34,8 +34,11 @@ METRIC = "sincos Gelem/s & % HBM roofline (fp32, 1 GPU); p50/p99 latency served"
 PMC_FILE = os.path.join(ROOT, "profiles", "plain_sincos_268M_pmc.json")
 # what determines the plain kernel's code and launch: its arithmetic, the
 # streaming helpers, its source and launcher, and the default launch shape
+# What the plain kernel's counter figures depend on: its device code and its
+# default launch shape (the LaunchShape definition in internal.hpp).
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_cs_0406049_amd", "csrc", f)
-                  for f in ("sincos_core.hpp", "stream.hpp", "plain.hip", "internal.hpp")]
+                  for f in ("sincos_core.hpp", "stream.hpp", "plain.hip")]
+LAUNCH_SHAPE_SOURCE = os.path.join(ROOT, "paper_cs_0406049_amd", "csrc", "internal.hpp")
 CEILING_SHAPES = ((64, 1, 0), (256, 1, 0), (512, 1, 0))
 
 
@@ -48,6 +51,10 @@ def kernel_source_hash() -> str:
     for p in KERNEL_SOURCES:
         with open(p, "rb") as f:
             h.update(f.read())
+    with open(LAUNCH_SHAPE_SOURCE, "rb") as f:
+        text = f.read()
+    start = text.index(b"struct LaunchShape {")
+    h.update(text[start:text.index(b"};", start) + 2])
     return h.hexdigest()
 
 
@@ -233,7 +240,7 @@ def bench_interleaved(torch, reps, plain_gbs, x_host):
     return res
 
 
-HUYGENS_OPS = 284 / 4   # VALU instructions per (point, source) pair in the loop's ISA
+HUYGENS_OPS = 142 / 2   # VALU instructions per (point, source) pair in the loop's ISA
 
 
 def bench_huygens(torch, reps):

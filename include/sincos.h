@@ -84,11 +84,13 @@ typedef enum {
     SINCOS_METHOD_ARCTAN = 1
 } sincos_method_t;
 
-/* Launch shape (0 in a field = library default).
- * block:  threads per workgroup, a multiple of 64 in [64, 1024]; default 256.
- * unroll: float4 per thread per loop trip (1, 2, 4 or 8); default 1.
- * grid:   workgroups; 0 = one per tile, covering the array once (grid-stride
- *         beyond 2^20 workgroups); for the ragged form 0 = one per unit. */
+/* Launch shape (0 in a field = the form's default: the built-in one below,
+ * or what sincos_set_tuning installed).
+ * block:  threads per workgroup, a multiple of 64 in [64, 1024]; built-in 256.
+ * unroll: float4 per thread per loop trip (1, 2, 4 or 8); built-in 1.
+ * grid:   workgroups; built-in 0 = one per tile, covering the array once
+ *         (grid-stride beyond 2^20 workgroups); for the ragged form one per
+ *         unit of work, and a smaller grid makes the launch persistent.     */
 typedef struct {
     int32_t block;
     int32_t unroll;
@@ -119,7 +121,7 @@ SINCOS_API int sincos_f32_interleaved(const float *x, float *out, int64_t n, int
                                       void *stream);
 
 /* ---------------------------------------------------------------------- */
-/* Ragged form: `count` independent arrays in ONE persistent kernel launch.
+/* Ragged form: `count` independent arrays in ONE kernel launch.
  * segs[j] = {x_j, s_j, c_j} (device pointers), lens[j] >= 0 its length.
  * Both tables are host memory, read before the call returns.  Each segment
  * obeys the plain form's aliasing rules; in addition no output may overlap
@@ -190,7 +192,9 @@ SINCOS_API int sinusoid_f32_forward(const float *t, int64_t N, const float *A, c
  * in binary32 per block of samples and combined in a fixed order, so the
  * result is deterministic.  gA, gw, gphi: [K] device outputs.  workspace:
  * device scratch of at least sinusoid_f32_backward_workspace_bytes(N, K)
- * bytes, owned by the caller, not aliasing anything else.                */
+ * bytes (3 * 64 ceil(K/64) ceil(N/8192) floats: one partial per 8192
+ * samples and frequency), owned by the caller, not aliasing anything else.
+ * EINVAL if N > 2^31 * 8192.                                              */
 SINCOS_API int64_t sinusoid_f32_backward_workspace_bytes(int64_t N, int32_t K);
 SINCOS_API int sinusoid_f32_backward(const float *t, const float *g, int64_t N, const float *A,
                           const float *w, const float *phi, int32_t K, float *gA, float *gw,

@@ -5,6 +5,7 @@
 #include "internal.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -696,7 +697,7 @@ extern "C" int64_t sinusoid_f32_backward_workspace_bytes(int64_t N, int32_t K)
 {
     if (N < 0 || K < 0)
         return -1;
-    return sinusoid_chunks(N) * 3 * sinusoid_kgroups(K) * 64 * (int64_t)sizeof(float);
+    return sinusoid_parts(N) * 3 * sinusoid_kgroups(K) * 64 * (int64_t)sizeof(float);
 }
 
 extern "C" int sinusoid_f32_backward(const float *t, const float *g, int64_t N, const float *A,
@@ -707,6 +708,8 @@ extern "C" int sinusoid_f32_backward(const float *t, const float *g, int64_t N, 
     clear_error();
     if (N < 0)
         return set_error(SINCOS_EINVAL, "sinusoid_f32_backward: N < 0");
+    if (sinusoid_parts(N) > INT32_MAX)
+        return set_error(SINCOS_EINVAL, "sinusoid_f32_backward: N too large");
     int rc = check_params(A, w, phi, K, "sinusoid_f32_backward");
     if (rc != SINCOS_OK)
         return rc;
@@ -736,6 +739,8 @@ extern "C" int huygens_f32(const float *xo, const float *yo, int64_t P, const fl
         return set_error(SINCOS_EINVAL, "huygens_f32: P < 0 or S < 0");
     if (P == 0)
         return SINCOS_OK;
+    if (P > (int64_t)INT32_MAX * 256)  // one 256-thread workgroup per 256 points
+        return set_error(SINCOS_EINVAL, "huygens_f32: P too large");
     if (!xo || !yo || !re || !im || (S > 0 && !src))
         return set_error(SINCOS_EINVAL, "huygens_f32: null pointer");
     if (!aligned4(xo) || !aligned4(yo) || !aligned4(re) || !aligned4(im) ||

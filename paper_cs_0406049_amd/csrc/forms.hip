@@ -213,12 +213,15 @@ __global__ void __launch_bounds__(256) k_sinusoid_fwd(const float *t, int64_t N,
 // K5: sinusoid adjoint.  Lane <-> frequency k (a wave covers 64 of them),
 // wave <-> chunk of consecutive samples: t_i and g_i are wave-uniform (scalar
 // loads), so each lane accumulates its own three sums with no cross-lane
-// traffic.  Partial sums go to partial[(j * Kpad + k) * nchunks + chunk]
-// (j = 0: A, 1: phi, 2: w); k_sinusoid_reduce adds each row in a fixed tree
-// order (deterministic) and applies A_k.
+// traffic.  The block's waves then add their sums in LDS in a fixed pairwise
+// tree, and the block writes one partial per (j, k) to
+// partial[(j * Kpad + k) * nparts + block] (j = 0: A, 1: phi, 2: w);
+// k_sinusoid_reduce adds each row in a fixed tree order (deterministic) and
+// applies A_k.
 
 constexpr int64_t kAdjChunk = 512;  // samples per wave
 constexpr int kAdjWaves = 16;       // waves per block (one chunk each)
+static_assert((kAdjWaves & (kAdjWaves - 1)) == 0 && kAdjWaves >= 3, "pairwise tree over the waves");
 
 __global__ void __launch_bounds__(64 * kAdjWaves) k_sinusoid_adj(const float *__restrict__ t,
                                                       const float *__restrict__ g, int64_t N,
@@ -226,46 +229,60 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_sinusoid_adj(const float *__
                                                       const float *__restrict__ phi, int32_t K,
                                                       int64_t nchunks, float *partial)
 {
+    __shared__ float sums[3][kAdjWaves][64];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t chunk = (int64_t)blockIdx.x * kAdjWaves + wave;
-    const int kg = blockIdx.y;
+    const int64_t nparts = gridDim.x;
     const int32_t Kpad = (int32_t)gridDim.y * 64;
-    const int32_t k = kg * 64 + lane;
-    if (chunk >= nchunks)
-        return;
+    const int32_t k = (int32_t)blockIdx.y * 64 + lane;
     const bool active = k < K;
     const float wk = active ? w[k] : 0.f;
     const float pk = active ? phi[k] : 0.f;
     float sa = 0.f, sp = 0.f, sw = 0.f;
-    const int64_t i0 = chunk * kAdjChunk;
-    const int64_t i1 = min(i0 + kAdjChunk, N);
+    if (chunk < nchunks) {  // waves past the last chunk add zeros
+        const int64_t i0 = chunk * kAdjChunk;
+        const int64_t i1 = min(i0 + kAdjChunk, N);
 #pragma unroll 8
-    for (int64_t i = i0; i < i1; ++i) {
-        const float ti = t[i], gi = g[i];
-        float sv, cv;
-        sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(wk, ti, pk), sv, cv);
-        sa = __builtin_fmaf(gi, sv, sa);
-        sp = __builtin_fmaf(gi, cv, sp);
-        sw = __builtin_fmaf(gi * ti, cv, sw);
+        for (int64_t i = i0; i < i1; ++i) {
+            const float ti = t[i], gi = g[i];
+            float sv, cv;
+            sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(wk, ti, pk), sv, cv);
+            sa = __builtin_fmaf(gi, sv, sa);
+            sp = __builtin_fmaf(gi, cv, sp);
+            sw = __builtin_fmaf(gi * ti, cv, sw);
+        }
     }
-    partial[((int64_t)0 * Kpad + k) * nchunks + chunk] = sa;
-    partial[((int64_t)1 * Kpad + k) * nchunks + chunk] = sp;
-    partial[((int64_t)2 * Kpad + k) * nchunks + chunk] = sw;
+    sums[0][wave][lane] = sa;
+    sums[1][wave][lane] = sp;
+    sums[2][wave][lane] = sw;
+    __syncthreads();
+    if (wave < 3) {  // wave j adds sum j over the block's waves
+        float v[kAdjWaves];
+#pragma unroll
+        for (int q = 0; q < kAdjWaves; ++q)
+            v[q] = sums[wave][q][lane];
+#pragma unroll
+        for (int h = kAdjWaves / 2; h > 0; h >>= 1)
+#pragma unroll
+            for (int q = 0; q < h; ++q)
+                v[q] = v[q] + v[q + h];
+        partial[((int64_t)wave * Kpad + k) * nparts + blockIdx.x] = v[0];
+    }
 }
 
-// One block per output (j, k): each thread sums a strided share of the row,
-// then a fixed-shape tree in LDS.
-__global__ void __launch_bounds__(256) k_sinusoid_reduce(const float *partial, int64_t nchunks,
+// One block per output (j, k): each thread sums a strided share of the row
+// of block partials, then a fixed-shape tree in LDS.
+__global__ void __launch_bounds__(256) k_sinusoid_reduce(const float *partial, int64_t nparts,
                                                          int32_t Kpad, int32_t K, const float *A,
                                                          float *gA, float *gw, float *gphi)
 {
     const int32_t k = blockIdx.x;
     const int j = blockIdx.y;  // 0: A, 1: phi, 2: w
     __shared__ float red[256];
-    const float *row = partial + ((int64_t)j * Kpad + k) * nchunks;
+    const float *row = partial + ((int64_t)j * Kpad + k) * nparts;
     float acc = 0.f;
-    for (int64_t ch = threadIdx.x; ch < nchunks; ch += blockDim.x)
+    for (int64_t ch = threadIdx.x; ch < nparts; ch += blockDim.x)
         acc += row[ch];
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -290,52 +307,63 @@ __global__ void __launch_bounds__(256) k_sinusoid_reduce(const float *partial, i
 // phi_j)), the path difference as rho^2 / (r + L).  Lane <-> screen point;
 // the source table (x, y, a, phi) is read with wave-uniform float4 scalar
 // loads; sources are summed in order with fma (so the only parallel axis is
-// the screen: one point per lane keeps the most waves resident, and the
-// unrolled source loop supplies the instruction-level parallelism).  sqrt and
+// the screen: one point per lane keeps the most waves resident).  The loads
+// of the next kHuyGroup sources are issued before the current group is
+// evaluated, so their latency hides behind that arithmetic.  sqrt and
 // division are IEEE (correctly rounded).
 
-constexpr int kHuyIPT = 1;
+constexpr int kHuyGroup = 2;
+
+__device__ __forceinline__ void huygens_term(float px, float py, f4 sq, float k, float L,
+                                             float L2, float &re, float &im)
+{
+    const float dx = px - sq.x;
+    const float dy = py - sq.y;
+    const float dy2 = dy * dy;
+    const float rho2 = __builtin_fmaf(dx, dx, dy2);
+    const float rr = __builtin_sqrtf(rho2 + L2);
+    const float d = rho2 / (rr + L);
+    float sv, cv;
+    sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(k, d, sq.w), sv, cv);
+    const float w = sq.z / rr;
+    re = __builtin_fmaf(w, cv, re);
+    im = __builtin_fmaf(w, sv, im);
+}
 
 __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *yo, int64_t P,
                                                  const f4 *__restrict__ src, int32_t S, float k,
                                                  float L, float L2, float *re, float *im)
 {
-    const int64_t bd = blockDim.x;
-    const int64_t base = (int64_t)blockIdx.x * bd * kHuyIPT + threadIdx.x;
-    float px[kHuyIPT], py[kHuyIPT], ar[kHuyIPT], ai[kHuyIPT];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const float px = i < P ? xo[i] : 0.f;
+    const float py = i < P ? yo[i] : 0.f;
+    float ar = 0.0f, ai = 0.0f;
+    const int32_t full = S / kHuyGroup * kHuyGroup;  // sources in whole groups
+    f4 cur[kHuyGroup];
+    if (full > 0) {
 #pragma unroll
-    for (int r = 0; r < kHuyIPT; ++r) {
-        const int64_t i = base + r * bd;
-        px[r] = i < P ? xo[i] : 0.f;
-        py[r] = i < P ? yo[i] : 0.f;
-        ar[r] = 0.0f;
-        ai[r] = 0.0f;
+        for (int u = 0; u < kHuyGroup; ++u)
+            cur[u] = src[u];
     }
-#pragma unroll 4
-    for (int32_t q = 0; q < S; ++q) {
-        const f4 sq = src[q];
+    for (int32_t q = 0; q < full; q += kHuyGroup) {
+        // the next group; the last group reloads itself, so every index is < S
+        const int32_t nq = min(q + kHuyGroup, full - kHuyGroup);
+        f4 nxt[kHuyGroup];
 #pragma unroll
-        for (int r = 0; r < kHuyIPT; ++r) {
-            const float dx = px[r] - sq.x;
-            const float dy = py[r] - sq.y;
-            const float dy2 = dy * dy;
-            const float rho2 = __builtin_fmaf(dx, dx, dy2);
-            const float rr = __builtin_sqrtf(rho2 + L2);
-            const float d = rho2 / (rr + L);
-            float sv, cv;
-            sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(k, d, sq.w), sv, cv);
-            const float w = sq.z / rr;
-            ar[r] = __builtin_fmaf(w, cv, ar[r]);
-            ai[r] = __builtin_fmaf(w, sv, ai[r]);
-        }
+        for (int u = 0; u < kHuyGroup; ++u)
+            nxt[u] = src[nq + u];
+#pragma unroll
+        for (int u = 0; u < kHuyGroup; ++u)
+            huygens_term(px, py, cur[u], k, L, L2, ar, ai);
+#pragma unroll
+        for (int u = 0; u < kHuyGroup; ++u)
+            cur[u] = nxt[u];
     }
-#pragma unroll
-    for (int r = 0; r < kHuyIPT; ++r) {
-        const int64_t i = base + r * bd;
-        if (i < P) {
-            re[i] = ar[r];
-            im[i] = ai[r];
-        }
+    for (int32_t q = full; q < S; ++q)
+        huygens_term(px, py, src[q], k, L, L2, ar, ai);
+    if (i < P) {
+        re[i] = ar;
+        im[i] = ai;
     }
 }
 
@@ -495,7 +523,7 @@ hipError_t launch_sinusoid_forward(const float *t, int64_t N, const float *A, co
 hipError_t launch_huygens(const float *xo, const float *yo, int64_t P, const float *src,
                           int32_t S, float k, float L, float *re, float *im, hipStream_t st)
 {
-    const int64_t per_block = 256 * kHuyIPT;
+    const int64_t per_block = 256;
     const int64_t grid = std::max<int64_t>(1, (P + per_block - 1) / per_block);
     const float L2 = L * L;
     hipLaunchKernelGGL(k_huygens, dim3((unsigned)grid), dim3(256), 0, st, xo, yo, P,
@@ -504,6 +532,7 @@ hipError_t launch_huygens(const float *xo, const float *yo, int64_t P, const flo
 }
 
 int64_t sinusoid_chunks(int64_t N) { return (N + kAdjChunk - 1) / kAdjChunk; }
+int64_t sinusoid_parts(int64_t N) { return (sinusoid_chunks(N) + kAdjWaves - 1) / kAdjWaves; }
 int64_t sinusoid_kgroups(int32_t K) { return std::max<int64_t>(1, ((int64_t)K + 63) / 64); }
 
 hipError_t launch_sinusoid_backward(const float *t, const float *g, int64_t N, const float *A,
@@ -511,18 +540,18 @@ hipError_t launch_sinusoid_backward(const float *t, const float *g, int64_t N, c
                                     float *gw, float *gphi, float *partial, hipStream_t st)
 {
     const int64_t nchunks = sinusoid_chunks(N);
+    const int64_t nparts = sinusoid_parts(N);  // one workgroup per kAdjWaves chunks
     const int64_t kg = sinusoid_kgroups(K);
     const int32_t Kpad = (int32_t)(kg * 64);
     if (nchunks > 0) {
-        const int64_t blocks = (nchunks + kAdjWaves - 1) / kAdjWaves;
-        hipLaunchKernelGGL(k_sinusoid_adj, dim3((unsigned)blocks, (unsigned)kg), dim3(64 * kAdjWaves),
+        hipLaunchKernelGGL(k_sinusoid_adj, dim3((unsigned)nparts, (unsigned)kg), dim3(64 * kAdjWaves),
                            0, st, t, g, N, w, phi, K, nchunks, partial);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
     }
     hipLaunchKernelGGL(k_sinusoid_reduce, dim3((unsigned)Kpad, 3), dim3(256), 0, st, partial,
-                       nchunks, Kpad, K, A, gA, gw, gphi);
+                       nparts, Kpad, K, A, gA, gw, gphi);
     return hipGetLastError();
 }
 

@@ -61,6 +61,7 @@ hipError_t launch_sinusoid_forward(const float *t, int64_t N, const float *A, co
 hipError_t launch_huygens(const float *xo, const float *yo, int64_t P, const float *src,
                           int32_t S, float k, float L, float *re, float *im, hipStream_t stream);
 int64_t sinusoid_chunks(int64_t N);
+int64_t sinusoid_parts(int64_t N);
 int64_t sinusoid_kgroups(int32_t K);
 hipError_t launch_sinusoid_backward(const float *t, const float *g, int64_t N, const float *A,
                                     const float *w, const float *phi, int32_t K, float *gA,

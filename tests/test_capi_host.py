@@ -144,8 +144,12 @@ def test_sinusoid_validation_and_workspace(L):
     assert L.sinusoid_f32_forward(None, 0, BASE, BASE, BASE, 3, None, None) == _capi.OK
     wb = L.sinusoid_f32_backward_workspace_bytes
     assert wb(-1, 4) == -1
-    assert wb(4_194_304, 64) == 8192 * 3 * 64 * 4      # 512-sample chunks, 64 lanes per group
-    assert wb(1025, 65) == 3 * 3 * 128 * 4
+    assert wb(4_194_304, 64) == 512 * 3 * 64 * 4       # one partial per 8192 samples and lane
+    assert wb(1025, 65) == 1 * 3 * 128 * 4
+    assert wb(8193, 1) == 2 * 3 * 64 * 4
+    rc = L.sinusoid_f32_backward(BASE, BASE, (1 << 31) * 8192 + 1, BASE, BASE, BASE, 4, BASE, BASE,
+                                 BASE, BASE, 1 << 40, None)
+    assert rc == _capi.EINVAL and "too large" in _capi.last_error()
     rc = L.sinusoid_f32_backward(BASE, BASE + 4096, 4096, BASE + 8192, BASE + 8192, BASE + 8192, 64,
                                  BASE + 9000, BASE + 10000, BASE + 11000, BASE + 20000, 16, None)
     assert rc == _capi.EINVAL and "workspace" in _capi.last_error()
@@ -197,3 +201,36 @@ def test_tuning_round_trip_and_rejection(L):
         assert _capi.get_tuning() == builtin
     finally:
         _capi.set_tuning(None)
+
+
+def test_huygens_validation(L):
+    f = L.huygens_f32
+    src = BASE + (1 << 20)          # 16-byte aligned source table
+    args = lambda P, S, xo=BASE, yo=BASE + 65536, s=src, kk=1.0, LL=100.0, re=BASE + 2 * 65536, \
+        im=BASE + 3 * 65536: (xo, yo, P, s, S, kk, LL, re, im, None)  # noqa: E731
+    assert f(*args(0, 0)) == _capi.OK
+    assert f(*args(-1, 4)) == _capi.EINVAL
+    assert f(*args(4, -1)) == _capi.EINVAL
+    assert f(*args(4, 4, xo=None)) == _capi.EINVAL
+    assert f(*args(4, 4, s=None)) == _capi.EINVAL
+    assert f(*args(4, 4, s=src + 4)) == _capi.EINVAL             # src not 16-byte aligned
+    assert f(*args(4, 4, re=BASE + 2 * 65536 + 2)) == _capi.EINVAL
+    for bad_L in (0.0, -1.0, float("inf"), float("nan")):
+        assert f(*args(4, 4, LL=bad_L)) == _capi.EINVAL, bad_L
+    assert f(*args(4, 4, im=BASE + 2 * 65536 + 8)) == _capi.EOVERLAP   # re and im overlap
+    assert f(*args(4, 4, re=BASE + 8)) == _capi.EOVERLAP              # re overlaps xo
+    assert f(*args(4, 4, im=src + 16)) == _capi.EOVERLAP              # im overlaps the sources
+    rc = f(*args((1 << 31) * 256, 4))
+    assert rc == _capi.EINVAL and "too large" in _capi.last_error()
+
+
+def test_interleaved_validation(L):
+    f = L.sincos_f32_interleaved
+    assert f(None, None, 0, 0, None) == _capi.OK
+    assert f(BASE, BASE + 4096, -1, 0, None) == _capi.EINVAL
+    assert f(BASE, BASE + 4096, 4, 2, None) == _capi.EINVAL          # unknown layout
+    assert f(None, BASE + 4096, 4, 0, None) == _capi.EINVAL
+    assert f(BASE + 4, BASE + 4096, 4, 0, None) == _capi.EINVAL      # not 16-byte aligned
+    assert f(BASE, BASE + 16, 8, 0, None) == _capi.EOVERLAP          # out overlaps x
+    # layout 1 writes 8 ceil(n/4) floats: for n = 5, out spans 64 bytes
+    assert f(BASE + 48, BASE, 5, 1, None) == _capi.EOVERLAP

@@ -281,15 +281,18 @@ def _sinusoid_small(N, K, seed):
 
 
 ADJ_CHUNK = 512   # samples per wave in the adjoint kernel
+ADJ_WAVES = 16    # waves per workgroup, summed in a pairwise tree
 
 
 def _adjoint_bound(N, abs_sum):
     """Rounding bound of the kernel's binary32 sums against exact sums:
-    per-wave recursive fma sums over at most ADJ_CHUNK samples, a strided
-    per-thread pass (at most ceil(chunks/256) terms) and an 8-level tree, plus
-    the rounding of g*t and of the final A_k product."""
+    per-wave recursive fma sums over at most ADJ_CHUNK samples, a 4-level
+    pairwise tree over the workgroup's waves, a strided per-thread pass over
+    the workgroup partials (at most ceil(parts/256) terms) and an 8-level tree,
+    plus the rounding of g*t and of the final A_k product."""
     chunks = max(1, -(-N // ADJ_CHUNK))
-    depth = min(N, ADJ_CHUNK) + -(-chunks // 256) + 8 + 3
+    parts = -(-chunks // ADJ_WAVES)
+    depth = min(N, ADJ_CHUNK) + (ADJ_WAVES.bit_length() - 1) + -(-parts // 256) + 8 + 3
     return depth * U * abs_sum * 1.001
 
 
