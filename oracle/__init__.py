@@ -81,6 +81,11 @@ def lib():
                                                     ctypes.POINTER(ctypes.c_int64)]
             L.oracle_error_scan_variant.argtypes = L.oracle_error_scan_reduced.argtypes
             L.oracle_pair_variant.argtypes = [ctypes.c_float, c_int, c_int, c_int, fp, fp]
+            L.oracle_pair_general.argtypes = [ctypes.c_float, c_int, c_int, fp, c_int, fp, c_int,
+                                              c_int, fp, fp]
+            L.oracle_error_scan_general.argtypes = [u32, u32, u32, c_int, c_int, fp, c_int, fp,
+                                                    c_int, c_int, c_int, dp, dp, dp, fp, fp,
+                                                    ctypes.POINTER(ctypes.c_int64)]
             L.oracle_sincos_backward_f32.argtypes = [fp, fp, fp, fp, fp, i64]
             L.oracle_sinusoid_forward_f32.argtypes = [fp, i64, fp, fp, fp, i32, fp, c_int, c_int,
                                                       c_int]
@@ -195,6 +200,34 @@ def pair_variant(q1: float, arith: int = FUSED, method: int = METHOD1,
     lib().oracle_pair_variant(ctypes.c_float(q1), arith, method, variant, ctypes.byref(s),
                               ctypes.byref(c))
     return np.float32(s.value), np.float32(c.value)
+
+
+def pair_general(q1: float, ndoub: int, ss, cc, arith: int = FUSED, fix: bool = True):
+    """The general-doubling ablation: series of len(ss), len(cc) terms for the
+    angle 2 pi q1 / 2^ndoub, then ndoub eq. (1) doublings (oracle_pair_general)."""
+    ss, cc = _c32(ss), _c32(cc)
+    s, c = ctypes.c_float(), ctypes.c_float()
+    lib().oracle_pair_general(ctypes.c_float(q1), arith, ndoub, _f32p(ss), ss.size, _f32p(cc),
+                              cc.size, int(fix), ctypes.byref(s), ctypes.byref(c))
+    return np.float32(s.value), np.float32(c.value)
+
+
+def error_scan_general(bits_lo: int, bits_hi: int, ndoub: int, ss, cc, stride: int = 1,
+                       arith: int = FUSED, fix: bool = True, threads: int | None = None):
+    """As error_scan_reduced, for pair_general."""
+    ss, cc = _c32(ss), _c32(cc)
+    mv, rv, ma = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    av, aa = ctypes.c_float(), ctypes.c_float()
+    cnt = ctypes.c_int64()
+    rc = lib().oracle_error_scan_general(bits_lo, bits_hi, stride, arith, ndoub, _f32p(ss),
+                                         ss.size, _f32p(cc), cc.size, int(fix),
+                                         threads or default_threads(), ctypes.byref(mv),
+                                         ctypes.byref(rv), ctypes.byref(ma), ctypes.byref(av),
+                                         ctypes.byref(aa), ctypes.byref(cnt))
+    if rc != 0:
+        raise ValueError("oracle_error_scan_general failed")
+    return dict(max_vec=mv.value, rms_vec=rv.value, max_amp=ma.value, argmax_vec=av.value,
+                argmax_amp=aa.value, count=cnt.value)
 
 
 def sincos_backward(s, c, gs=None, gc=None):

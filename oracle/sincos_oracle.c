@@ -242,6 +242,56 @@ void oracle_pair_variant(float q1, int arith, int method, int variant, float *s,
 }
 
 /* ---------------------------------------------------------------------- */
+/* Ablation: the number of doublings against the series length (analysis
+ * only).  Sec. II argues that each eq. (1) doubling keeps the relative angle
+ * error and squares the magnitude, so a series over a smaller angle (shorter,
+ * for the same fit error) can be followed by more doublings, at the price of
+ * a magnitude drift and first-pair rounding that grow with 2^n.  Here the
+ * series approximate sin and cos of 2 pi q1 / 2^n (n = ndoub; n = 2 is the
+ * method, whose quarter angle is pi q1 / 2):
+ *   s1 = q1 (ss[0] + ss[1] q2 + ... + ss[ns-1] q2^(ns-1))
+ *   c1 = 1 + q2 (cc[0] + cc[1] q2 + ... + cc[nc-1] q2^(nc-1))
+ * by Horner in q2 as in step 2.  Then n doublings with eq. (1).  With fix,
+ * the factor 2 - s^2 - c^2 is taken from the pair that precedes the last
+ * doubling: that pair's squared magnitude is the final magnitude a^(2^n), as
+ * the pair after doubling 1 is for n = 2 in Fig. 1.  For n = 0 the text's
+ * (3 - s^2 - c^2) / 2 is applied to the series pair instead.  With n = 2,
+ * the first method's coefficients and fix, this is step 2-4 exactly.       */
+void oracle_pair_general(float q1, int arith, int ndoub, const float *ss, int ns,
+                         const float *cc, int nc, int fix, float *s, float *c)
+{
+    float q2 = q1 * q1;
+    float t = ss[ns - 1];
+    for (int k = ns - 2; k >= 0; k--)
+        t = mul_add(q2, t, ss[k], arith);
+    float sv = q1 * t;
+    float u = cc[nc - 1];
+    for (int k = nc - 2; k >= 0; k--)
+        u = mul_add(q2, u, cc[k], arith);
+    float cv = mul_add(q2, u, 1.0f, arith);
+    float m = 1.0f;
+    if (ndoub == 0 && fix) {
+        float h = mul_sub_from(sv, sv, mul_sub_from(cv, cv, 3.0f, arith), arith);
+        m = 0.5f * h;
+    }
+    for (int d = 0; d < ndoub; d++) {
+        if (fix && d == ndoub - 1)
+            m = oracle_magnitude_factor(sv, cv, arith, ORACLE_METHOD1);
+        float s2, c2;
+        oracle_double_angle(sv, cv, arith, &s2, &c2);
+        sv = s2;
+        cv = c2;
+    }
+    if (fix) {
+        *s = sv * m;
+        *c = cv * m;
+    } else {
+        *s = sv;
+        *c = cv;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
 /* Array drivers.  A plain loop over elements; with threads > 1 the array is
  * cut into contiguous chunks, each run by the same scalar loop.  Each worker
  * first installs the default floating-point environment (round to nearest,
@@ -385,6 +435,9 @@ struct scan_job {
     int arith, method, variant;
     struct err_stats *per_chunk; /* one slot per chunk start */
     int64_t per;                 /* chunk length, to find the slot */
+    /* oracle_pair_general's parameters when general != 0 */
+    int general, ndoub, ns, nc, fix;
+    const float *ss, *cc;
 };
 
 static void scan_chunk(void *job, int64_t lo, int64_t hi)
@@ -397,7 +450,9 @@ static void scan_chunk(void *job, int64_t lo, int64_t hi)
         float q;
         memcpy(&q, &bits, sizeof q);
         float s, c;
-        if (j->variant == ORACLE_VARIANT_LISTING)
+        if (j->general)
+            oracle_pair_general(q, j->arith, j->ndoub, j->ss, j->ns, j->cc, j->nc, j->fix, &s, &c);
+        else if (j->variant == ORACLE_VARIANT_LISTING)
             oracle_pair_from_reduced(q, j->arith, j->method, &s, &c);
         else
             oracle_pair_variant(q, j->arith, j->method, j->variant, &s, &c);
@@ -437,14 +492,13 @@ int oracle_error_scan_reduced(uint32_t bits_lo, uint32_t bits_hi, uint32_t strid
                                      out_argmax_vec, out_argmax_amp, out_count);
 }
 
-int oracle_error_scan_variant(uint32_t bits_lo, uint32_t bits_hi, uint32_t stride, int arith,
-                              int method, int variant, int threads, double *out_max_vec,
-                              double *out_rms_vec, double *out_max_amp, float *out_argmax_vec,
-                              float *out_argmax_amp, int64_t *out_count)
+static int run_scan(struct scan_job *j, int threads, double *out_max_vec, double *out_rms_vec,
+                    double *out_max_amp, float *out_argmax_vec, float *out_argmax_amp,
+                    int64_t *out_count)
 {
-    if (stride == 0 || bits_hi < bits_lo)
+    if (j->stride == 0 || j->bits_hi < j->bits_lo)
         return -1;
-    int64_t n = (int64_t)((bits_hi - bits_lo) / stride) + 1;
+    int64_t n = (int64_t)((j->bits_hi - j->bits_lo) / j->stride) + 1;
     if (threads < 1)
         threads = 1;
     if (threads > 256)
@@ -453,9 +507,9 @@ int oracle_error_scan_variant(uint32_t bits_lo, uint32_t bits_hi, uint32_t strid
         threads = (int)n;
     struct err_stats slots[256];
     memset(slots, 0, sizeof slots);
-    struct scan_job j = {bits_lo, bits_hi, stride, arith, method, variant, slots,
-                         (n + threads - 1) / threads};
-    run_chunks(scan_chunk, &j, n, threads);
+    j->per_chunk = slots;
+    j->per = (n + threads - 1) / threads;
+    run_chunks(scan_chunk, j, n, threads);
     struct err_stats tot = {0.0, 0.0, 0.0, 0.0f, 0.0f, 0};
     for (int i = 0; i < threads; i++) {
         tot.sum_sq_vec += slots[i].sum_sq_vec;
@@ -476,6 +530,50 @@ int oracle_error_scan_variant(uint32_t bits_lo, uint32_t bits_hi, uint32_t strid
     *out_argmax_amp = tot.argmax_amp;
     *out_count = tot.count;
     return 0;
+}
+
+int oracle_error_scan_variant(uint32_t bits_lo, uint32_t bits_hi, uint32_t stride, int arith,
+                              int method, int variant, int threads, double *out_max_vec,
+                              double *out_rms_vec, double *out_max_amp, float *out_argmax_vec,
+                              float *out_argmax_amp, int64_t *out_count)
+{
+    struct scan_job j;
+    memset(&j, 0, sizeof j);
+    j.bits_lo = bits_lo;
+    j.bits_hi = bits_hi;
+    j.stride = stride;
+    j.arith = arith;
+    j.method = method;
+    j.variant = variant;
+    return run_scan(&j, threads, out_max_vec, out_rms_vec, out_max_amp, out_argmax_vec,
+                    out_argmax_amp, out_count);
+}
+
+/* The same statistics for oracle_pair_general (1 <= ns, nc <= 16,
+ * 0 <= ndoub <= 16).                                                        */
+int oracle_error_scan_general(uint32_t bits_lo, uint32_t bits_hi, uint32_t stride, int arith,
+                              int ndoub, const float *ss, int ns, const float *cc, int nc,
+                              int fix, int threads, double *out_max_vec, double *out_rms_vec,
+                              double *out_max_amp, float *out_argmax_vec,
+                              float *out_argmax_amp, int64_t *out_count)
+{
+    if (ns < 1 || ns > 16 || nc < 1 || nc > 16 || ndoub < 0 || ndoub > 16 || !ss || !cc)
+        return -1;
+    struct scan_job j;
+    memset(&j, 0, sizeof j);
+    j.bits_lo = bits_lo;
+    j.bits_hi = bits_hi;
+    j.stride = stride;
+    j.arith = arith;
+    j.general = 1;
+    j.ndoub = ndoub;
+    j.ns = ns;
+    j.nc = nc;
+    j.fix = fix;
+    j.ss = ss;
+    j.cc = cc;
+    return run_scan(&j, threads, out_max_vec, out_rms_vec, out_max_amp, out_argmax_vec,
+                    out_argmax_amp, out_count);
 }
 
 /* ---------------------------------------------------------------------- */

@@ -71,3 +71,97 @@ def test_variant_scans(orc):
           for v in (oracle.VARIANT_LISTING, oracle.VARIANT_TEXT_FIX, oracle.VARIANT_EQ2)}
     assert abs(st[oracle.VARIANT_TEXT_FIX]["max_vec"] / st[oracle.VARIANT_LISTING]["max_vec"] - 1) < 0.02
     assert st[oracle.VARIANT_EQ2]["max_vec"] > 1.4 * st[oracle.VARIANT_LISTING]["max_vec"]
+
+
+# ---------------------------------------------------------------------------
+# The number of doublings against the series length (oracle_pair_general).
+
+PRINTED_SS = np.array([1.5707963235, -0.645963615, 0.0796819754, -0.0046075748], np.float32)
+PRINTED_CC = np.array([-1.2336977925, 0.2536086171, -0.0204391631], np.float32)
+HALF = 0x3F000000          # bit pattern of 0.5: the reduced angles [0, 1/2]
+
+
+def test_general_form_reduces_to_the_method(orc):
+    """n = 2 doublings with the first method's printed coefficients is steps
+    2-4 exactly, with and without the fix, in both arithmetics."""
+    rng = np.random.default_rng(7)
+    qs = np.concatenate([rng.uniform(-0.5, 0.5, 3000), [0.0, 0.25, -0.25, 0.5, -0.5, 1e-40]])
+    qs = qs.astype(np.float32)
+    for arith in (oracle.FUSED, oracle.SPLIT):
+        s_ref, c_ref = oracle.pair_from_reduced(qs, arith)
+        for i, q in enumerate(qs):
+            got = oracle.pair_general(float(q), 2, PRINTED_SS, PRINTED_CC, arith)
+            assert got == (s_ref[i], c_ref[i]), (q, arith)
+        for q in qs[:300]:
+            assert oracle.pair_general(float(q), 2, PRINTED_SS, PRINTED_CC, arith, fix=False) == \
+                oracle.pair_variant(float(q), arith, oracle.METHOD1, oracle.VARIANT_NO_FIX)
+
+
+def test_refit_reproduces_the_papers_series_and_accuracy(orc):
+    """The least-squares refit for n = 2 with 4 sine and 3 cosine terms lands
+    next to the printed coefficients and, through the binary32 sequence,
+    within 10 % of the printed maximum error 4.8e-7 (Sec. II)."""
+    from oracle import series_fit
+    ss, cc = series_fit.fit_series(2, 4, 3)
+    assert np.all(np.abs(ss[:3] / PRINTED_SS[:3] - 1) < 1e-4)
+    assert np.all(np.abs(cc[:2] / PRINTED_CC[:2] - 1) < 1e-4)
+    assert abs(ss[3] / PRINTED_SS[3] - 1) < 5e-3 and abs(cc[2] / PRINTED_CC[2] - 1) < 5e-3
+    fit_s, fit_c = series_fit.fit_residual(2, ss, cc)
+    pr_s, pr_c = series_fit.fit_residual(2, PRINTED_SS, PRINTED_CC)
+    assert fit_s < 2 * pr_s and fit_c < 2 * pr_c
+    r = oracle.error_scan_general(0, HALF, 2, ss, cc, stride=61)
+    assert abs(r["max_vec"] / 4.8e-7 - 1) < 0.10, r
+
+
+@pytest.fixture(scope="module")
+def converged(orc):
+    """Scan statistics with series long enough that the fit error is far
+    below binary32 rounding (8 sine, 8 cosine terms), n = 1..5."""
+    from oracle import series_fit
+    out = {}
+    for n in range(1, 6):
+        ss, cc = series_fit.fit_series(n, 8, 8)
+        out[n] = (oracle.error_scan_general(0, HALF, n, ss, cc, stride=257),
+                  oracle.error_scan_general(0, HALF, n, ss, cc, stride=257, fix=False))
+    return out
+
+
+def test_unfixed_magnitude_drift_doubles_per_doubling(converged):
+    """Each eq. (1) doubling squares the magnitude, so a first-pair magnitude
+    1 + e ends as (1 + e)^(2^n): the drift doubles with every doubling once
+    it dominates the rounding each doubling adds (from n = 3 on here).  The
+    text writes the exponent as 2n, the same number at n = 2; the measured
+    growth follows 2^n (ratios 2, not (n + 1) / n)."""
+    amp = {n: converged[n][1]["max_amp"] for n in converged}
+    assert all(amp[n] > amp[n - 1] for n in range(2, 6)), amp
+    for n in (4, 5):
+        assert 1.8 < amp[n] / amp[n - 1] < 2.2, amp
+
+
+def test_fix_holds_the_magnitude_at_every_doubling_count(converged):
+    for n, (fixed, unfixed) in converged.items():
+        assert fixed["max_amp"] < 1.8e-7, (n, fixed)
+        if n >= 2:
+            assert unfixed["max_amp"] > 2 * fixed["max_amp"], (n, unfixed, fixed)
+
+
+def test_angle_error_floor_grows_with_doublings(converged):
+    """The doublings keep the relative angle error, so the rounding of the
+    first pair is carried into a 2^n times larger angle: with converged
+    series the error floor rises with n."""
+    mx = {n: converged[n][0]["max_vec"] for n in converged}
+    assert mx[1] < mx[2] < mx[3] < mx[4], mx
+    assert mx[4] > 1.5 * mx[2]
+
+
+def test_fewer_doublings_need_longer_series(orc):
+    """At n = 2 the paper's lengths (4, 3) reach its accuracy; the same
+    lengths at n = 1 do not, and n = 3 gets there with (3, 3)."""
+    from oracle import series_fit
+    def max_err(n, ns, nc):
+        ss, cc = series_fit.fit_series(n, ns, nc)
+        return oracle.error_scan_general(0, HALF, n, ss, cc, stride=257)["max_vec"]
+    assert max_err(2, 4, 3) < 5e-7
+    assert max_err(1, 4, 3) > 1e-5
+    assert max_err(2, 3, 3) > 2e-6
+    assert max_err(3, 3, 3) < 6e-7
