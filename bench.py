@@ -178,6 +178,32 @@ def bench_adjoint(torch, reps, plain_gbs):
             "per_byte_vs_plain": round(gbs / plain_gbs, 4)}
 
 
+# The pair-ceiling kernel's loop: 208 VALU instructions per trip of 8 pairs.
+PAIR_CEILING_OPS = 208 / 8
+
+
+def valu_ceiling(torch):
+    """Measured VALU rate (T lane-ops/s) of the pair's instruction mix with no
+    memory traffic: sincos_pair_ceiling_f32 over 2^21 lanes x 256 steps x 8
+    chains (several rounds of the chip's resident waves).  Taken right after
+    the kernel it is compared with, so both see the same clocks."""
+    from paper_cs_0406049_amd import _capi
+    n, steps = 1 << 21, 256
+    x = torch.rand(n, device="cuda")
+    out = torch.empty_like(x)
+    ms, _ = time_launches(torch, lambda: _capi.sincos_pair_ceiling_f32(x, out, n, steps), 5, 2)
+    tops = n * steps * 8 * PAIR_CEILING_OPS / (ms * 1e-3) / 1e12
+    log("VALU ceiling (pair mix, no memory): %.3f ms, %.1f T lane-ops/s" % (ms, tops))
+    return tops
+
+
+def alu_roofline(tops, ops_per_pair, ceil):
+    return {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
+            "unit": "Tops/s (VALU lane-ops)", "frac": round(tops / VALU_PEAK_TOPS, 4),
+            "ops_per_pair": ops_per_pair, "measured_ceiling_Tops": round(ceil, 2),
+            "frac_of_measured_ceiling": round(tops / ceil, 4)}
+
+
 def bench_sinusoid(torch, reps):
     from paper_cs_0406049_amd import _capi, workloads
     from paper_cs_0406049_amd.autograd import sinusoid_loss_and_grads
@@ -194,6 +220,7 @@ def bench_sinusoid(torch, reps):
     a_ms, _ = time_launches(torch, lambda: _capi.sinusoid_f32_backward(
         t, r, A, w, phi, gA, gw, gp, ws, nb), reps, 2)
     tot_ms, _ = time_launches(torch, lambda: sinusoid_loss_and_grads(t, yobs, A, w, phi), reps, 2)
+    ceil = valu_ceiling(torch)
     # composed baseline: theta matrix in torch, the plain kernel over it, then
     # rocBLAS products for the model and its gradients
     theta = torch.empty(K, N, device="cuda")
@@ -216,10 +243,8 @@ def bench_sinusoid(torch, reps):
             "loss_and_grads_ms": round(tot_ms, 4), "composed_plain_kernel_plus_torch_ms":
             round(c_ms, 4), "speedup_vs_composed": round(c_ms / tot_ms, 2),
             "pairs_per_s": round(2 * pairs / (tot_ms * 1e-3), 1),
-            "roofline": {"bound": "alu", "achieved": round(ops / (tot_ms * 1e-3) / 1e12, 2),
-                         "peak": round(VALU_PEAK_TOPS, 2), "unit": "Tops/s (VALU lane-ops)",
-                         "frac": round(ops / (tot_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS, 4),
-                         "ops_per_pair": [SINUSOID_FWD_OPS, SINUSOID_ADJ_OPS]}}
+            "roofline": alu_roofline(ops / (tot_ms * 1e-3) / 1e12,
+                                     [SINUSOID_FWD_OPS, SINUSOID_ADJ_OPS], ceil)}
 
 
 def bench_interleaved(torch, reps, plain_gbs, x_host):
@@ -256,6 +281,7 @@ def bench_huygens(torch, reps):
     re = torch.empty_like(xo)
     im = torch.empty_like(xo)
     ms, _ = time_launches(torch, lambda: _capi.huygens_f32(xo, yo, src, p.k, p.L, re, im), reps, 1)
+    ceil = valu_ceiling(torch)
     sx, sy, sa, sp = (src.view(S, 4)[:, i] for i in range(4))
     chunk = 1 << 16
     th = torch.empty(chunk, S, device="cuda")
@@ -284,9 +310,7 @@ def bench_huygens(torch, reps):
             "kernel_ms": round(ms, 4), "pairs_per_s": round(pairs / (ms * 1e-3), 1),
             "composed_plain_kernel_plus_torch_ms": round(c_ms, 3),
             "speedup_vs_composed": round(c_ms / ms, 2),
-            "roofline": {"bound": "alu", "achieved": round(tops, 2), "peak": round(VALU_PEAK_TOPS, 2),
-                         "unit": "Tops/s (VALU lane-ops)", "frac": round(tops / VALU_PEAK_TOPS, 4),
-                         "ops_per_pair": HUYGENS_OPS}}
+            "roofline": alu_roofline(tops, HUYGENS_OPS, ceil)}
 
 
 def bench_serve(torch, plain_gelem_s):

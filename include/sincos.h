@@ -224,6 +224,17 @@ SINCOS_API int huygens_f32(const float *xo, const float *yo, int64_t P, const fl
 SINCOS_API int sincos_copy_ceiling_f32(const float *x, float *s, float *c, int64_t n,
                             const sincos_launch_t *launch, void *stream);
 
+/* Measurement helper: the VALU ceiling of the pair's instruction mix.  Lane i
+ * runs 8 independent chains theta_r = x[i] + r (r = 0..7), adding 1 per step,
+ * for `reps` steps; each step takes the pair (FUSED, NORMALIZED) of every
+ * theta_r and adds its sine and cosine to two binary32 running sums (plain
+ * adds, in step order).  out[i] = sum over r = 0..7, in order, of
+ * (sines_r + cosines_r).  Register-only between one load and one store per
+ * lane.  x and out: [n] device arrays, 4-byte aligned; out == x is allowed,
+ * any other overlap is EOVERLAP.  n < 0 or reps < 0 is EINVAL.            */
+SINCOS_API int sincos_pair_ceiling_f32(const float *x, float *out, int64_t n, int32_t reps,
+                                       void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Request server: continuous batching of sine-cosine requests of any size.
  *

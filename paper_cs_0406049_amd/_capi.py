@@ -94,6 +94,7 @@ _SIGNATURES = {
                                              _P]),
     "sincos_copy_ceiling_f32": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(Launch), _P]),
     "sincos_f32_interleaved": (ctypes.c_int, [_P, _P, _I64, _I32, _P]),
+    "sincos_pair_ceiling_f32": (ctypes.c_int, [_P, _P, _I64, _I32, _P]),
     "huygens_f32": (ctypes.c_int, [_P, _P, _I64, _P, _I32, ctypes.c_float, ctypes.c_float, _P, _P,
                                    _P]),
     "sincos_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)]),
@@ -219,6 +220,11 @@ def sincos_f32_interleaved(x, out, n=None, layout=0, stream=None) -> None:
 def sincos_copy_ceiling_f32(x, s, c, n=None, launch=None, stream=None) -> None:
     _check(lib().sincos_copy_ceiling_f32(_ptr(x), _ptr(s), _ptr(c), _numel(x, n),
                                          _launch(launch), _stream(stream)))
+
+
+def sincos_pair_ceiling_f32(x, out, n=None, reps=1, stream=None) -> None:
+    _check(lib().sincos_pair_ceiling_f32(_ptr(x), _ptr(out), _numel(x, n), int(reps),
+                                         _stream(stream)))
 
 
 def _seg_tables(segs, lens):

@@ -444,6 +444,28 @@ extern "C" int sincos_copy_ceiling_f32(const float *x, float *s, float *c, int64
     return e == hipSuccess ? SINCOS_OK : hip_error(e, "sincos_copy_ceiling_f32: kernel launch");
 }
 
+extern "C" int sincos_pair_ceiling_f32(const float *x, float *out, int64_t n, int32_t reps,
+                                       void *stream)
+{
+    clear_error();
+    if (n < 0 || reps < 0)
+        return set_error(SINCOS_EINVAL, "sincos_pair_ceiling_f32: n < 0 or reps < 0");
+    if (n == 0)
+        return SINCOS_OK;
+    if (n > (int64_t)INT32_MAX * 256)
+        return set_error(SINCOS_EINVAL, "sincos_pair_ceiling_f32: n too large");
+    if (!x || !out || !aligned4(x) || !aligned4(out))
+        return set_error(SINCOS_EINVAL, "sincos_pair_ceiling_f32: null or misaligned pointer");
+    if (ranges_overlap(x, n, out, n) && x != out)
+        return set_error(SINCOS_EOVERLAP, "sincos_pair_ceiling_f32: x partly overlaps out");
+    const DeviceInfo *dev;
+    int rc;
+    if ((rc = current_device(&dev)) != SINCOS_OK)
+        return rc;
+    hipError_t e = launch_pair_ceiling(x, out, n, reps, (hipStream_t)stream);
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "sincos_pair_ceiling_f32: kernel launch");
+}
+
 // ---------------------------------------------------------------------------
 // Ragged form
 

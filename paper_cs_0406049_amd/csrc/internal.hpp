@@ -51,6 +51,8 @@ hipError_t launch_sincos_interleaved(const float *x, float *out, int64_t n, int 
                                      hipStream_t stream);
 hipError_t launch_copy_ceiling(const float *x, float *s, float *c, int64_t n,
                                const LaunchShape &shape, hipStream_t stream);
+hipError_t launch_pair_ceiling(const float *x, float *out, int64_t n, int32_t reps,
+                               hipStream_t stream);
 hipError_t launch_ragged(const RaggedDesc *desc, const int64_t *ubeg, int32_t count,
                          int64_t total_units, int arith, int method, const LaunchShape &shape,
                          hipStream_t stream);

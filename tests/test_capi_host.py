@@ -162,6 +162,18 @@ def test_copy_ceiling_validation(L):
     assert f(BASE, BASE, BASE + 8192, 4, None, None) == _capi.EOVERLAP
 
 
+def test_pair_ceiling_validation(L):
+    f = L.sincos_pair_ceiling_f32
+    assert f(None, None, 0, 4, None) == _capi.OK
+    assert f(BASE, BASE + 4096, -1, 4, None) == _capi.EINVAL
+    assert f(BASE, BASE + 4096, 4, -1, None) == _capi.EINVAL
+    assert f(None, BASE + 4096, 4, 1, None) == _capi.EINVAL
+    assert f(BASE + 2, BASE + 4096, 4, 1, None) == _capi.EINVAL
+    assert f(BASE, BASE + 8, 4, 1, None) == _capi.EOVERLAP
+    rc = f(BASE, BASE + 4096, (1 << 31) * 256, 1, None)
+    assert rc == _capi.EINVAL and "too large" in _capi.last_error()
+
+
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     """No silent fallback: without the built library the binding raises."""
     monkeypatch.setattr(_capi, "LIB_PATH", str(tmp_path / "missing.so"))

@@ -234,3 +234,39 @@ def test_interleaved_layouts(torch_dev, layout):
                 assert np.array_equal(blocks[b, :m].view(np.uint32), sp[4 * b:4 * b + m].view(np.uint32)), (n, b)
                 assert np.array_equal(blocks[b, 4:4 + m].view(np.uint32), cp[4 * b:4 * b + m].view(np.uint32)), (n, b)
         assert np.all(oh[out_len:].view(np.uint32) == CANARY), n
+
+
+def _pair_ceiling_reference(xh, reps):
+    """The ceiling kernel's sums written out with the oracle's pair and binary32
+    adds: 8 chains theta_r = x + r, +1 per step, sines and cosines summed in
+    step order, then sum over r of (sines_r + cosines_r)."""
+    one = np.float32(1.0)
+    th = [(xh + np.float32(r)).astype(np.float32) for r in range(8)]
+    ss = [np.zeros_like(xh) for _ in range(8)]
+    cs = [np.zeros_like(xh) for _ in range(8)]
+    for _ in range(reps):
+        for r in range(8):
+            s, c = oracle.sincos(th[r], FUSED, 0)
+            ss[r] = (ss[r] + s).astype(np.float32)
+            cs[r] = (cs[r] + c).astype(np.float32)
+            th[r] = (th[r] + one).astype(np.float32)
+    o = np.zeros_like(xh)
+    for r in range(8):
+        o = (o + (ss[r] + cs[r]).astype(np.float32)).astype(np.float32)
+    return o
+
+
+@pytest.mark.parametrize("n,reps", [(1, 1), (777, 3), (4096, 2), (65537, 1), (300, 0)])
+def test_pair_ceiling_kernel_matches_its_definition(torch_dev, n, reps):
+    """The VALU-ceiling measurement kernel computes what its header says (its
+    pairs are the method's, bit for bit)."""
+    torch = torch_dev
+    from paper_cs_0406049_amd import _capi
+    xh = np.random.default_rng(n).uniform(-50, 50, n).astype(np.float32)
+    x = torch.from_numpy(xh).cuda()
+    out = torch.from_numpy(np.full(n + 64, CANARY, np.uint32).view(np.float32)).cuda()
+    _capi.sincos_pair_ceiling_f32(x, out, n, reps)
+    torch.cuda.synchronize()
+    oh = out.cpu().numpy()
+    assert_bit_exact(oh[:n], _pair_ceiling_reference(xh, reps), "pair ceiling n=%d" % n, xh)
+    assert np.all(oh[n:].view(np.uint32) == CANARY)
