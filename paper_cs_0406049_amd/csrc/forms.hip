@@ -368,6 +368,44 @@ __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *y
 }
 
 // ---------------------------------------------------------------------------
+// K7: VALU ceiling for the pair's instruction mix: lane i runs kCeilChains
+// independent angle chains theta_r = x_i + r, each step adding 1, for `reps`
+// steps, and sums the sines and the cosines of each chain in binary32 in step
+// order; out[i] = sum over r, in order, of (sines_r + cosines_r).  Nothing but
+// registers between the one load and the one store, so its rate is the VALU's.
+constexpr int kCeilChains = 8;
+
+__global__ void __launch_bounds__(256) k_pair_ceiling(const float *x, float *out, int64_t n,
+                                                      int32_t reps)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const float x0 = i < n ? x[i] : 0.0f;
+    float th[kCeilChains], sums[kCeilChains], sumc[kCeilChains];
+#pragma unroll
+    for (int r = 0; r < kCeilChains; ++r) {
+        th[r] = x0 + (float)r;
+        sums[r] = 0.0f;
+        sumc[r] = 0.0f;
+    }
+    for (int32_t j = 0; j < reps; ++j) {
+#pragma unroll
+        for (int r = 0; r < kCeilChains; ++r) {
+            float sv, cv;
+            sincos_pair<Arith::Fused, Method::Normalized>(th[r], sv, cv);
+            sums[r] = sums[r] + sv;
+            sumc[r] = sumc[r] + cv;
+            th[r] = th[r] + 1.0f;
+        }
+    }
+    float o = 0.0f;
+#pragma unroll
+    for (int r = 0; r < kCeilChains; ++r)
+        o = o + (sums[r] + sumc[r]);
+    if (i < n)
+        out[i] = o;
+}
+
+// ---------------------------------------------------------------------------
 // Launchers.
 
 namespace {
@@ -552,6 +590,14 @@ hipError_t launch_sinusoid_backward(const float *t, const float *g, int64_t N, c
     }
     hipLaunchKernelGGL(k_sinusoid_reduce, dim3((unsigned)Kpad, 3), dim3(256), 0, st, partial,
                        nparts, Kpad, K, A, gA, gw, gphi);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_ceiling(const float *x, float *out, int64_t n, int32_t reps,
+                               hipStream_t st)
+{
+    const int64_t grid = (n + 255) / 256;
+    hipLaunchKernelGGL(k_pair_ceiling, dim3((unsigned)grid), dim3(256), 0, st, x, out, n, reps);
     return hipGetLastError();
 }
 
