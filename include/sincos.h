@@ -303,7 +303,9 @@ SINCOS_API int sincos_server_release(sincos_server_t *srv, int64_t id);
 SINCOS_API int sincos_server_stats(const sincos_server_t *srv, sincos_server_stats_t *out);
 /* Submit request j at start + arrival_ns[j] from a generator thread, wait
  * for every completion and store it in out[j].  With auto_release off each
- * request is released once its completion is stored.                     */
+ * request is released once its completion is stored.  Request j carries tag
+ * j and the replay consumes every completion it polls, so nothing else may
+ * submit to or poll the server while a replay runs.                       */
 SINCOS_API int sincos_server_replay(sincos_server_t *srv, const float *const *xs,
                                     const int64_t *ns, const int64_t *arrival_ns, int32_t count,
                                     sincos_completion_t *out);

@@ -345,12 +345,18 @@ int ragged_enqueue(const RaggedTable &t, int arith, int method, const LaunchShap
     if (!slot.done && hipEventCreateWithFlags(&slot.done, hipEventDisableTiming) != hipSuccess)
         return set_error(SINCOS_EHIP, "ragged: cannot create an event");
     rc = stage_and_launch(t, slot.buf.host, slot.buf.dev, arith, method, shape, dev, stream);
+    // Guard the slot even when the launch failed: the staging copy may already
+    // be enqueued and still read the pinned buffer.
+    e = hipEventRecord(slot.done, stream);
+    if (e == hipSuccess)
+        slot.pending = true;
     if (rc != SINCOS_OK)
         return rc;
-    e = hipEventRecord(slot.done, stream);
-    if (e != hipSuccess)
+    if (e != hipSuccess) {
+        // the slot cannot be proven idle any more: wait for the stream instead
+        (void)hipStreamSynchronize(stream);
         return hip_error(e, "ragged: event record");
-    slot.pending = true;
+    }
     return SINCOS_OK;
 }
 
@@ -403,7 +409,7 @@ extern "C" int sincos_f32_interleaved(const float *x, float *out, int64_t n, int
         return set_error(SINCOS_EINVAL, "sincos_f32_interleaved: null pointer with n > 0");
     if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(out)) & 15)
         return set_error(SINCOS_EINVAL, "sincos_f32_interleaved: x and out must be 16-byte aligned");
-    if (n > (int64_t(1) << 60))
+    if (n > (int64_t)INT32_MAX * 1024)  // one 256-thread workgroup per 1024 elements
         return set_error(SINCOS_EINVAL, "sincos_f32_interleaved: n too large");
     // out holds 2n floats (layout 1 rounds the last block up to 8 floats)
     const int64_t out_floats = layout == 0 ? 2 * n : 8 * ((n + 3) / 4);

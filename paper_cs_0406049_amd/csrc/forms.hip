@@ -552,7 +552,10 @@ hipError_t launch_sinusoid_forward(const float *t, int64_t N, const float *A, co
                                    const float *phi, int32_t K, float *y, hipStream_t st)
 {
     const int64_t per_block = 256 * kFwdIPT;
-    const int64_t grid = std::max<int64_t>(1, (N + per_block - 1) / per_block);
+    // one tile of samples per workgroup; the kernel's grid-stride loop covers
+    // any N beyond 2^20 workgroups
+    const int64_t grid =
+        std::max<int64_t>(1, std::min<int64_t>((N + per_block - 1) / per_block, int64_t(1) << 20));
     hipLaunchKernelGGL(k_sinusoid_fwd, dim3((unsigned)grid), dim3(256), 0, st, t, N, A, w, phi, K,
                        y);
     return hipGetLastError();

@@ -62,6 +62,9 @@ public:
     virtual int launch(int slot, const std::vector<Request *> &batch) = 0;
     virtual int query(int slot) = 0;
     virtual void wait(int slot) = 0;
+    // After a failed launch: wait for whatever part of it was enqueued, so
+    // that its memory can be reused.
+    virtual void drain(int slot) = 0;
     virtual char *arena_base() = 0;
 };
 
@@ -73,6 +76,8 @@ public:
     }
     ~GpuExecutor() override
     {
+        int prev = -1;
+        const bool restore = hipGetDevice(&prev) == hipSuccess && prev != device_;
         (void)hipSetDevice(device_);
         for (auto &sl : slots_) {
             if (sl.stream)
@@ -85,6 +90,8 @@ public:
         }
         if (arena_)
             (void)hipFree(arena_);
+        if (restore)
+            (void)hipSetDevice(prev);  // the destroying thread keeps its device
     }
     int init(int slots) override
     {
@@ -146,6 +153,7 @@ public:
         return SINCOS_EHIP;
     }
     void wait(int slot) override { (void)hipEventSynchronize(slots_[slot].done); }
+    void drain(int slot) override { (void)hipStreamSynchronize(slots_[slot].stream); }
     char *arena_base() override { return arena_; }
 
 private:
@@ -198,6 +206,7 @@ public:
         while (now_ns() < deadline_[slot])
             std::this_thread::yield();
     }
+    void drain(int) override {}
     char *arena_base() override { return reinterpret_cast<char *>(uintptr_t(1) << 40); }
 
 private:
@@ -405,6 +414,8 @@ struct sincos_server {
                     r->batch_requests = (int32_t)take;
                 }
                 const int rc = exec->launch((int)k, sl.batch);
+                if (rc != SINCOS_OK)
+                    exec->drain((int)k);  // before the batch's outputs return to the arena
                 std::lock_guard<std::mutex> lk(mu);
                 if (rc != SINCOS_OK) {
                     for (Request *r : sl.batch)

@@ -91,14 +91,17 @@ def test_arrival_order_no_overtaking():
 def test_continuous_batching_and_overlap():
     """Requests arriving while batches run join later batches; up to
     max_inflight batches are on the executor at once."""
+    # 400 arrivals 20 us apart (an 8 ms stream), 300 us batches, 3 in flight:
+    # about one launch per 100 us with ~5 requests each.  The bounds leave
+    # room for the host scheduler delaying threads by a millisecond or so.
     count = 400
-    arr = np.arange(count, dtype=np.int64) * 10_000      # one every 10 us
+    arr = np.arange(count, dtype=np.int64) * 20_000
     ns = np.full(count, 5000, np.int64)
-    with sim(max_inflight=3, sim_batch_ns=100_000, auto_release=True) as s:
+    with sim(max_inflight=3, sim_batch_ns=300_000, auto_release=True) as s:
         out = s.replay([FAKE] * count, ns, arr)
         st = s.stats()
     assert np.all(out["status"] == 0)
-    assert st["batches"] < count / 3                       # batched
+    assert st["batches"] < count / 2                       # batched
     assert st["batches"] > 5                                # continuously, not once
     assert st["inflight_peak"] == 3                         # overlapped
     assert out["batch_requests"].max() > 1
@@ -107,8 +110,8 @@ def test_continuous_batching_and_overlap():
     assert np.all(out["t_submit_ns"] <= out["t_admit_ns"])
     assert np.all(out["t_admit_ns"] <= out["t_launch_ns"])
     assert np.all(out["t_launch_ns"] < out["t_complete_ns"])
-    # latency is bounded by a few batch times, not by the whole stream
-    assert np.percentile(lat, 99) < 20 * 100_000
+    # latency is bounded by a few batch times, not by the whole 8 ms stream
+    assert np.percentile(lat, 99) < 4_000_000
 
 
 def test_batch_caps():
