@@ -149,8 +149,10 @@ def _check(status: int) -> int:
     return status
 
 
-def _ptr(a):
-    """Device address of a tensor (float32, contiguous, on the GPU) or an int."""
+def _ptr(a, need=None):
+    """Device address of a tensor (float32, contiguous, on the GPU) or an int.
+    A tensor must hold at least `need` elements when that is given (a raw
+    address is taken as is)."""
     if a is None:
         return None
     if isinstance(a, int):
@@ -161,15 +163,22 @@ def _ptr(a):
         raise ValueError("array must be float32")
     if not a.is_contiguous():
         raise ValueError("array must be contiguous")
+    if need is not None and a.numel() < need:
+        raise ValueError("array holds %d elements, the call needs %d" % (a.numel(), need))
     return a.data_ptr()
 
 
-def _raw_ptr(a):
-    """Device address of a tensor of any dtype, an int, or None."""
+def _raw_ptr(a, need_bytes=None):
+    """Device address of a contiguous tensor of any dtype, an int, or None."""
     if a is None or isinstance(a, int):
         return a
     if not a.is_cuda:
         raise ValueError("array must be on the GPU")
+    if not a.is_contiguous():
+        raise ValueError("array must be contiguous")
+    if need_bytes is not None and a.numel() * a.element_size() < need_bytes:
+        raise ValueError("array holds %d bytes, the call needs %d"
+                         % (a.numel() * a.element_size(), need_bytes))
     return a.data_ptr()
 
 
@@ -202,28 +211,34 @@ def _numel(a, n):
 
 
 def sincos_f32(x, s, c, n=None, stream=None) -> None:
-    _check(lib().sincos_f32(_ptr(x), _ptr(s), _ptr(c), _numel(x, n), _stream(stream)))
+    n = _numel(x, n)
+    _check(lib().sincos_f32(_ptr(x, n), _ptr(s, n), _ptr(c, n), n, _stream(stream)))
 
 
 def sincos_f32_ex(x, s, c, n=None, arith=ARITH_FUSED, method=METHOD_NORMALIZED, launch=None,
                   stream=None) -> None:
-    _check(lib().sincos_f32_ex(_ptr(x), _ptr(s), _ptr(c), _numel(x, n), int(arith), int(method),
+    n = _numel(x, n)
+    _check(lib().sincos_f32_ex(_ptr(x, n), _ptr(s, n), _ptr(c, n), n, int(arith), int(method),
                                _launch(launch), _stream(stream)))
 
 
 def sincos_f32_interleaved(x, out, n=None, layout=0, stream=None) -> None:
     """layout 0: complex64 (cos, sin) pairs; 1: blocks of 4 sines, 4 cosines."""
-    _check(lib().sincos_f32_interleaved(_ptr(x), _raw_ptr(out), _numel(x, n), int(layout),
+    n = _numel(x, n)
+    out_floats = 2 * n if int(layout) == 0 else 8 * ((n + 3) // 4)
+    _check(lib().sincos_f32_interleaved(_ptr(x, n), _raw_ptr(out, 4 * out_floats), n, int(layout),
                                         _stream(stream)))
 
 
 def sincos_copy_ceiling_f32(x, s, c, n=None, launch=None, stream=None) -> None:
-    _check(lib().sincos_copy_ceiling_f32(_ptr(x), _ptr(s), _ptr(c), _numel(x, n),
+    n = _numel(x, n)
+    _check(lib().sincos_copy_ceiling_f32(_ptr(x, n), _ptr(s, n), _ptr(c, n), n,
                                          _launch(launch), _stream(stream)))
 
 
 def sincos_pair_ceiling_f32(x, out, n=None, reps=1, stream=None) -> None:
-    _check(lib().sincos_pair_ceiling_f32(_ptr(x), _ptr(out), _numel(x, n), int(reps),
+    n = _numel(x, n)
+    _check(lib().sincos_pair_ceiling_f32(_ptr(x, n), _ptr(out, n), n, int(reps),
                                          _stream(stream)))
 
 
@@ -233,12 +248,15 @@ def _seg_tables(segs, lens):
     import numpy as np
     count = len(segs)
     tab = np.zeros((max(count, 1), 3), np.uint64)
-    if count:
-        tab[:count] = [[_ptr(x) or 0, _ptr(s) or 0, _ptr(c) or 0] for x, s, c in segs]
     if lens is None:
         lt = np.array([int(x.numel()) for x, _, _ in segs] or [0], np.int64)
     else:
         lt = np.ascontiguousarray(lens, np.int64) if count else np.zeros(1, np.int64)
+        if lt.shape != (count,) and count:
+            raise ValueError("lens must hold one length per segment")
+    if count:
+        tab[:count] = [[_ptr(x, n) or 0, _ptr(s, n) or 0, _ptr(c, n) or 0]
+                       for (x, s, c), n in zip(segs, lt[:count].tolist())]
     st = tab.ctypes.data_as(ctypes.POINTER(Seg))
     lp = lt.ctypes.data_as(ctypes.POINTER(_I64))
     return (st, tab), (lp, lt), count
@@ -293,13 +311,15 @@ class RaggedPlan:
 
 
 def sincos_f32_backward(s, c, gs, gc, gx, n=None, stream=None) -> None:
-    _check(lib().sincos_f32_backward(_ptr(s), _ptr(c), _ptr(gs), _ptr(gc), _ptr(gx),
-                                     _numel(s, n), _stream(stream)))
+    n = _numel(s, n)
+    _check(lib().sincos_f32_backward(_ptr(s, n), _ptr(c, n), _ptr(gs, n), _ptr(gc, n),
+                                     _ptr(gx, n), n, _stream(stream)))
 
 
 def sinusoid_f32_forward(t, A, w, phi, y, N=None, K=None, stream=None) -> None:
-    _check(lib().sinusoid_f32_forward(_ptr(t), _numel(t, N), _ptr(A), _ptr(w), _ptr(phi),
-                                      _numel(A, K), _ptr(y), _stream(stream)))
+    N, K = _numel(t, N), _numel(A, K)
+    _check(lib().sinusoid_f32_forward(_ptr(t, N), N, _ptr(A, K), _ptr(w, K), _ptr(phi, K), K,
+                                      _ptr(y, N), _stream(stream)))
 
 
 def sinusoid_f32_backward_workspace_bytes(N: int, K: int) -> int:
@@ -312,8 +332,9 @@ def sinusoid_f32_backward(t, g, A, w, phi, gA, gw, gphi, workspace, workspace_by
     K = _numel(A, K)
     if workspace_bytes is None:
         workspace_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
-    _check(lib().sinusoid_f32_backward(_ptr(t), _ptr(g), N, _ptr(A), _ptr(w), _ptr(phi), K,
-                                       _ptr(gA), _ptr(gw), _ptr(gphi), _raw_ptr(workspace),
+    _check(lib().sinusoid_f32_backward(_ptr(t, N), _ptr(g, N), N, _ptr(A, K), _ptr(w, K),
+                                       _ptr(phi, K), K, _ptr(gA, K), _ptr(gw, K), _ptr(gphi, K),
+                                       _raw_ptr(workspace, int(workspace_bytes)),
                                        int(workspace_bytes), _stream(stream)))
 
 
@@ -321,8 +342,8 @@ def huygens_f32(xo, yo, src, k, L, re, im, P=None, S=None, stream=None) -> None:
     """src: [S, 4] float32 (x, y, amplitude, phase), 16-byte aligned."""
     P = _numel(xo, P)
     S = int(S if S is not None else src.numel() // 4)
-    _check(lib().huygens_f32(_ptr(xo), _ptr(yo), P, _ptr(src), S, float(k), float(L), _ptr(re),
-                             _ptr(im), _stream(stream)))
+    _check(lib().huygens_f32(_ptr(xo, P), _ptr(yo, P), P, _ptr(src, 4 * S), S, float(k),
+                             float(L), _ptr(re, P), _ptr(im, P), _stream(stream)))
 
 
 def set_tuning(shapes) -> None:

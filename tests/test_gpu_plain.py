@@ -270,3 +270,29 @@ def test_pair_ceiling_kernel_matches_its_definition(torch_dev, n, reps):
     oh = out.cpu().numpy()
     assert_bit_exact(oh[:n], _pair_ceiling_reference(xh, reps), "pair ceiling n=%d" % n, xh)
     assert np.all(oh[n:].view(np.uint32) == CANARY)
+
+
+def test_binding_rejects_short_arrays(torch_dev):
+    """The binding checks that every tensor holds what the call will touch,
+    before anything reaches the device."""
+    torch = torch_dev
+    from paper_cs_0406049_amd import _capi
+    x = torch.zeros(100, device="cuda")
+    short = torch.zeros(99, device="cuda")
+    ok = torch.zeros(100, device="cuda")
+    with pytest.raises(ValueError):
+        _capi.sincos_f32(x, short, ok)
+    with pytest.raises(ValueError):
+        _capi.sincos_f32(x, ok, ok.clone(), n=101)
+    with pytest.raises(ValueError):
+        _capi.sincos_f32_interleaved(x, torch.zeros(199, device="cuda"), layout=0)
+    with pytest.raises(ValueError):
+        _capi.sincos_f32_interleaved(x[:5], torch.zeros(15, device="cuda"), layout=1)
+    with pytest.raises(ValueError):
+        _capi.sincos_f32_backward(x, ok, short, None, ok.clone())
+    with pytest.raises(ValueError):
+        _capi.sincos_f32_ragged([(x, ok, short)], [100])
+    with pytest.raises(ValueError):
+        _capi.huygens_f32(x, ok, torch.zeros(7, device="cuda"), 1.0, 10.0, ok.clone(), ok.clone(),
+                          S=2)
+    torch.cuda.synchronize()
