@@ -139,8 +139,10 @@ def bench_ragged(torch, reps, plain_gbs):
     elems = int(lens.sum())
     shape = autotune.tune_ragged(segs, lens, cache_path=None, reps=3)
     plan = _capi.RaggedPlan(segs, lens, launch=shape)
-    g_ms, _ = time_launches(torch, plan.graph_launch, reps, 2)
-    k_ms, _ = time_launches(torch, plan.launch, reps, 2)
+    # steady state: a graph launch costs ~15 us more than the bare kernel
+    # when launches are back to back, more for the first few
+    k_ms, _ = time_launches(torch, plan.launch, max(20, reps), 3)
+    g_ms, _ = time_launches(torch, plan.graph_launch, max(20, reps), 3)
     one_ms, _ = time_launches(torch, lambda: _capi.sincos_f32_ragged(segs, lens), reps, 2)
 
     def per_array():
