@@ -412,6 +412,7 @@ def main(argv=None):
         ev_ms, wall_ms, value, achieved))
 
     ceiling = None
+    references = None
     if not args.no_ceiling:
         # the same 1-read / 2-write float4 stream with no arithmetic, best of a
         # few launch shapes
@@ -422,6 +423,13 @@ def main(argv=None):
             gbs = BYTES_PER_ELEM * n / (cev * 1e-3) / 1e9
             log("copy ceiling (1 read : 2 writes) %s: %.4f ms, %.0f GB/s" % (shape, cev, gbs))
             ceiling = gbs if ceiling is None else max(ceiling, gbs)
+        # references from the runtime and torch: a device-to-device copy
+        # (1 read : 1 write) and a fill (writes only), same array size
+        cp_ms, _ = time_launches(torch, lambda: s.copy_(x), args.steps, args.warmup)
+        fill_ms, _ = time_launches(torch, lambda: s.fill_(0.5), args.steps, args.warmup)
+        references = {"torch_copy_1r1w_GBps": round(8 * n / (cp_ms * 1e-3) / 1e9, 1),
+                      "torch_fill_write_only_GBps": round(4 * n / (fill_ms * 1e-3) / 1e9, 1)}
+        log("references: %s" % references)
         step()  # leave the sine-cosine outputs in s, c
         torch.cuda.synchronize()
 
@@ -451,7 +459,8 @@ def main(argv=None):
                      "kernel_ms": round(ev_ms, 5),
                      "measured_ceiling_GBps": None if ceiling is None else round(ceiling, 1),
                      "frac_of_measured_ceiling": None if ceiling is None else
-                     round(achieved / ceiling, 4)},
+                     round(achieved / ceiling, 4),
+                     "references": references},
     }
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
