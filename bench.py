@@ -35,7 +35,7 @@ PMC_FILE = os.path.join(ROOT, "profiles", "plain_sincos_268M_pmc.json")
 # what determines the plain kernel's code and launch: its arithmetic, the
 # streaming helpers, its source and launcher, and the default launch shape
 # What the plain kernel's counter figures depend on: its device code and its
-# default launch shape (the LaunchShape definition in internal.hpp).
+# default launch shape (LaunchShape and kBuiltinShape in internal.hpp).
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_cs_0406049_amd", "csrc", f)
                   for f in ("sincos_core.hpp", "stream.hpp", "plain.hip")]
 LAUNCH_SHAPE_SOURCE = os.path.join(ROOT, "paper_cs_0406049_amd", "csrc", "internal.hpp")
@@ -54,7 +54,8 @@ def kernel_source_hash() -> str:
     with open(LAUNCH_SHAPE_SOURCE, "rb") as f:
         text = f.read()
     start = text.index(b"struct LaunchShape {")
-    h.update(text[start:text.index(b"};", start) + 2])
+    end = text.index(b";", text.index(b"kBuiltinShape[2] =", start)) + 1
+    h.update(text[start:end])
     return h.hexdigest()
 
 
@@ -434,6 +435,7 @@ def main(argv=None):
         torch.cuda.synchronize()
 
     traffic = counter_traffic(n)
+    default_plain = _capi.get_tuning()["plain"]
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -449,8 +451,10 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": wl, "n": n, "bytes_per_elem": BYTES_PER_ELEM,
                    "arith": args.arith, "method": "normalized (first method)",
-                   "launch": {"block": args.block or 256, "unroll": args.unroll or 1,
-                              "grid": args.grid or "one workgroup per tile"},
+                   "launch": {"block": args.block or default_plain["block"],
+                              "unroll": args.unroll or default_plain["unroll"],
+                              "grid": args.grid or default_plain["grid"] or
+                              "one workgroup per tile"},
                    "device": props.name, "cus": props.multi_processor_count},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),

@@ -86,7 +86,8 @@ typedef enum {
 
 /* Launch shape (0 in a field = the form's default: the built-in one below,
  * or what sincos_set_tuning installed).
- * block:  threads per workgroup, a multiple of 64 in [64, 1024]; built-in 256.
+ * block:  threads per workgroup, a multiple of 64 in [64, 1024]; built-in 64
+ *         for the plain form, 256 for the ragged form.
  * unroll: float4 per thread per loop trip (1, 2, 4 or 8); built-in 1.
  * grid:   workgroups; built-in 0 = one per tile, covering the array once
  *         (grid-stride beyond 2^20 workgroups); for the ragged form one per
@@ -322,7 +323,8 @@ SINCOS_API int sincos_server_destroy(sincos_server_t *srv);
  * json: a JSON object {"plain": {...}, "ragged": {...}}, each holding any of
  *       the integer fields "block", "unroll", "grid" with the meanings and
  *       limits of sincos_launch_t.  Forms and fields left out get the
- *       built-in defaults (256, 1, 0), so NULL or "{}" restores them.
+ *       built-in defaults (plain 64, 1, 0; ragged 256, 1, 0), so NULL or
+ *       "{}" restores them.
  * Errors: EINVAL for text outside that form (unknown keys, non-integers,
  * trailing text) or values out of range; the current shapes are then kept.
  * Thread-safe.  Takes effect for calls that start after it returns; plans

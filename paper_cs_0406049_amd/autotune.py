@@ -24,7 +24,7 @@ from . import _capi
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mi355_sincos", "tune.json")
 
-BLOCKS = (256, 512)
+BLOCKS = (64, 128, 256, 512)
 UNROLLS = (1, 2, 4)
 # resident waves per CU for a persistent grid (grid = CUs * waves / (block / 64));
 # 0 = one workgroup per unit of work (no persistence)

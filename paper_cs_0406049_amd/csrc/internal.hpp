@@ -22,8 +22,8 @@ struct RaggedDesc {
 };
 static_assert(sizeof(RaggedDesc) == 48, "descriptor layout");
 
-// Default: 256 threads, one float4 per thread, one tile per workgroup (the
-// fastest measured shape for the 1-read / 2-write stream on MI355X).
+// A launch shape: threads per workgroup, float4 per thread per loop trip,
+// workgroups (0 = one per tile / unit of work).
 struct LaunchShape {
     int block = 256;
     int unroll = 1;
@@ -32,6 +32,13 @@ struct LaunchShape {
 
 // Process-wide defaults per form, installed by sincos_set_tuning.
 enum { kFormPlain = 0, kFormRagged = 1 };
+
+// Built-in defaults (what sincos_set_tuning(NULL) restores).  Plain form: one
+// 64-thread wave per workgroup, one float4 per thread, one tile per
+// workgroup -- the fastest measured shape for its 1-read / 2-write stream on
+// MI355X (3 % ahead of 256 threads).  Ragged form: 256 threads, where the
+// per-unit segment lookup is amortized over more work.
+constexpr LaunchShape kBuiltinShape[2] = {{64, 1, 0}, {256, 1, 0}};
 LaunchShape default_shape(int form);
 int validate_shape(const LaunchShape &sh, const char *who);
 

@@ -5,13 +5,15 @@
 // The accepted text is a small JSON subset:
 //   {"plain": {"block": 256, "unroll": 1, "grid": 0},
 //    "ragged": {"block": 512, "unroll": 2, "grid": 0}}
-// Both forms and all three fields are optional; a missing field keeps the
-// built-in default.  Anything else (unknown keys, non-integers, trailing
-// text) is rejected, leaving the current shapes unchanged.
+// Both forms and all three fields are optional; a missing field takes the
+// built-in default (kBuiltinShape).  Anything else (unknown keys,
+// non-integers, trailing text) is rejected, leaving the current shapes
+// unchanged.
 #include "../../include/sincos.h"
 #include "internal.hpp"
 
 #include <cctype>
+#include <climits>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -20,7 +22,7 @@
 namespace mi355 {
 
 static std::mutex g_tune_mu;
-static LaunchShape g_tuned[2];  // [kFormPlain], [kFormRagged]
+static LaunchShape g_tuned[2] = {kBuiltinShape[kFormPlain], kBuiltinShape[kFormRagged]};
 
 LaunchShape default_shape(int form)
 {
@@ -96,7 +98,7 @@ struct Reader {
         long long v = 0;
         while (std::isdigit((unsigned char)*p)) {
             v = v * 10 + (*p++ - '0');
-            if (v > (1LL << 31))
+            if (v > (1LL << 31) || (!neg && v > INT_MAX))
                 return fail("integer out of range");
         }
         if (*p == '.' || *p == 'e' || *p == 'E')
@@ -181,7 +183,8 @@ using namespace mi355;
 extern "C" int sincos_set_tuning(const char *json)
 {
     clear_error();
-    LaunchShape next[2];  // built-in defaults; fields present in json override
+    // built-in defaults; fields present in json override
+    LaunchShape next[2] = {kBuiltinShape[kFormPlain], kBuiltinShape[kFormRagged]};
     if (json) {
         Reader r{json, {}};
         if (!r.document(next))
