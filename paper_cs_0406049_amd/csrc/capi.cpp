@@ -409,7 +409,7 @@ extern "C" int sincos_f32_interleaved(const float *x, float *out, int64_t n, int
         return set_error(SINCOS_EINVAL, "sincos_f32_interleaved: null pointer with n > 0");
     if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(out)) & 15)
         return set_error(SINCOS_EINVAL, "sincos_f32_interleaved: x and out must be 16-byte aligned");
-    if (n > (int64_t)INT32_MAX * 1024)  // one 256-thread workgroup per 1024 elements
+    if (n > (int64_t)INT32_MAX * 512)  // one 128-thread workgroup per 512 elements
         return set_error(SINCOS_EINVAL, "sincos_f32_interleaved: n too large");
     // out holds 2n floats (layout 1 rounds the last block up to 8 floats)
     const int64_t out_floats = layout == 0 ? 2 * n : 8 * ((n + 3) / 4);

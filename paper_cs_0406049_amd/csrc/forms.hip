@@ -17,16 +17,21 @@ namespace mi355 {
 //   LAYOUT 0: complex64 e^{ix}: out[2i] = cos x_i, out[2i + 1] = sin x_i
 //   LAYOUT 1: the paper's phase blocks: per 4 elements, 4 sines then 4 cosines
 // x and out 16-byte aligned; n4 = n / 4 whole blocks (the caller does the
-// tail).  Block size is fixed at 256 (4 waves).
+// tail).  Two waves per workgroup: measured on MI355X at 6.6 TB/s, against
+// 6.4 with one or four.
+
+constexpr int kIntWaves = 2;
 
 template <int LAYOUT>
-__global__ void __launch_bounds__(256) k_sincos_interleaved(const f4 *x, f4 *out, int64_t n4)
+__global__ void __launch_bounds__(64 * kIntWaves) k_sincos_interleaved(const f4 *x, f4 *out,
+                                                                      int64_t n4)
 {
-    __shared__ f4 stage[4][128];
+    __shared__ f4 stage[kIntWaves][128];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t wbase = (int64_t)blockIdx.x * 256 + wave * 64;  // first float4 of x for this wave
+    const int64_t i = (int64_t)blockIdx.x * (64 * kIntWaves) + threadIdx.x;
+    // first float4 of x for this wave
+    const int64_t wbase = (int64_t)blockIdx.x * (64 * kIntWaves) + wave * 64;
     if (wbase >= n4)
         return;  // whole wave past the end (wave-uniform)
     f4 so = f4{0.f, 0.f, 0.f, 0.f}, co = so;
@@ -135,25 +140,42 @@ __device__ __forceinline__ float adjoint1(float s, float c, float gs, float gc)
     return a - b;
 }
 
+// Float4 body: one float4 per lane, one 64-thread wave per workgroup and
+// tile (grid-stride past 2^20 tiles), buffer loads and stores with the
+// non-temporal policy -- measured on MI355X at 6.5 TB/s against 6.1 for
+// 512-thread workgroups of global loads and stores.
+constexpr int kBwdBlock = 64;
+constexpr int kBwdStorePolicy = 2;  // nt
+
 template <bool GS, bool GC>
-__global__ void __launch_bounds__(512) k_backward_vec(const f4 *s, const f4 *c, const f4 *gs,
-                                                      const f4 *gc, f4 *gx, int64_t n4)
+__global__ void __launch_bounds__(kBwdBlock) k_backward_vec(const f4 *s, const f4 *c,
+                                                            const f4 *gs, const f4 *gc, f4 *gx,
+                                                            int64_t n4)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
-        const f4 sv = __builtin_nontemporal_load(s + i);
-        const f4 cv = __builtin_nontemporal_load(c + i);
+    const int bd = blockDim.x;
+    const int off = (int)threadIdx.x * 16;
+    for (int64_t t0 = (int64_t)blockIdx.x * bd; t0 < n4; t0 += (int64_t)gridDim.x * bd) {
+        // the tile's byte range: lanes past the end load 0 and store nothing
+        const int64_t bytes = min<int64_t>(bd, n4 - t0) * 16;
+        auto load = [&](const f4 *p) {
+            return __builtin_bit_cast(
+                f4, __builtin_amdgcn_raw_buffer_load_b128(tile_rsrc(p + t0, bytes), off, 0,
+                                                          kLoadPolicy));
+        };
+        const f4 sv = load(s);
+        const f4 cv = load(c);
         f4 a = f4{0.f, 0.f, 0.f, 0.f}, b = f4{0.f, 0.f, 0.f, 0.f};
         if (GS)
-            a = __builtin_nontemporal_load(gs + i);
+            a = load(gs);
         if (GC)
-            b = __builtin_nontemporal_load(gc + i);
+            b = load(gc);
         f4 r;
         r.x = adjoint1<GS, GC>(sv.x, cv.x, a.x, b.x);
         r.y = adjoint1<GS, GC>(sv.y, cv.y, a.y, b.y);
         r.z = adjoint1<GS, GC>(sv.z, cv.z, a.z, b.z);
         r.w = adjoint1<GS, GC>(sv.w, cv.w, a.w, b.w);
-        __builtin_nontemporal_store(r, gx + i);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, r), tile_rsrc(gx + t0, bytes),
+                                               off, 0, kBwdStorePolicy);
     }
 }
 
@@ -438,13 +460,14 @@ hipError_t launch_sincos_interleaved(const float *x, float *out, int64_t n, int 
 {
     const int64_t n4 = n / 4;
     if (n4 > 0) {
-        const int64_t grid = (n4 + 255) / 256;
+        const int per_block = 64 * kIntWaves;
+        const int64_t grid = (n4 + per_block - 1) / per_block;
         if (layout == 0)
-            hipLaunchKernelGGL(k_sincos_interleaved<0>, dim3((unsigned)grid), dim3(256), 0, st,
-                               reinterpret_cast<const f4 *>(x), reinterpret_cast<f4 *>(out), n4);
+            hipLaunchKernelGGL(k_sincos_interleaved<0>, dim3((unsigned)grid), dim3(per_block), 0,
+                               st, reinterpret_cast<const f4 *>(x), reinterpret_cast<f4 *>(out), n4);
         else
-            hipLaunchKernelGGL(k_sincos_interleaved<1>, dim3((unsigned)grid), dim3(256), 0, st,
-                               reinterpret_cast<const f4 *>(x), reinterpret_cast<f4 *>(out), n4);
+            hipLaunchKernelGGL(k_sincos_interleaved<1>, dim3((unsigned)grid), dim3(per_block), 0,
+                               st, reinterpret_cast<const f4 *>(x), reinterpret_cast<f4 *>(out), n4);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
@@ -532,15 +555,16 @@ hipError_t launch_backward(const float *s, const float *c, const float *gs, cons
     }
     scalar(0, head);
     // one float4 per thread, one tile per workgroup (grid-stride past 2^20)
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((n4 + 511) / 512, int64_t(1) << 20));
+    const int64_t grid = std::max<int64_t>(
+        1, std::min<int64_t>((n4 + kBwdBlock - 1) / kBwdBlock, int64_t(1) << 20));
     const f4 *sv = reinterpret_cast<const f4 *>(s + head);
     const f4 *cv = reinterpret_cast<const f4 *>(c + head);
     const f4 *gsv = gs ? reinterpret_cast<const f4 *>(gs + head) : nullptr;
     const f4 *gcv = gc ? reinterpret_cast<const f4 *>(gc + head) : nullptr;
     f4 *gxv = reinterpret_cast<f4 *>(gx + head);
 #define MI355_BWD_V(GS, GC)                                                                       \
-    hipLaunchKernelGGL((k_backward_vec<GS, GC>), dim3((unsigned)grid), dim3(512), 0, st, sv, cv, \
-                       gsv, gcv, gxv, n4)
+    hipLaunchKernelGGL((k_backward_vec<GS, GC>), dim3((unsigned)grid), dim3(kBwdBlock), 0, st, \
+                       sv, cv, gsv, gcv, gxv, n4)
     if (gs && gc) MI355_BWD_V(true, true);
     else if (gs) MI355_BWD_V(true, false);
     else if (gc) MI355_BWD_V(false, true);

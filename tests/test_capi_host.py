@@ -247,5 +247,5 @@ def test_interleaved_validation(L):
     assert f(BASE, BASE + 16, 8, 0, None) == _capi.EOVERLAP          # out overlaps x
     # layout 1 writes 8 ceil(n/4) floats: for n = 5, out spans 64 bytes
     assert f(BASE + 48, BASE, 5, 1, None) == _capi.EOVERLAP
-    rc = f(BASE, BASE + (1 << 44), (1 << 31) * 1024, 0, None)
+    rc = f(BASE, BASE + (1 << 44), (1 << 31) * 512, 0, None)
     assert rc == _capi.EINVAL and "too large" in _capi.last_error()
