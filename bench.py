@@ -366,8 +366,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the plain form shards into independent ranges; see the design notes). "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the plain form would shard into independent contiguous ranges, one per GPU). "
               "Run with --gpus 1.", file=sys.stderr)
         return 2
 

@@ -85,7 +85,7 @@ def _scan(L, arith, stride):
 
 
 def failed_pins(L):
-    """Names of the pins this build fails."""
+    """Names of the pins that this compiled copy of the oracle fails."""
     from oracle import exact_binary32 as ex
     bad = []
     # constants against the printed decimals
