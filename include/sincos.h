@@ -185,6 +185,23 @@ SINCOS_API int sincos_f32_backward(const float *s, const float *c, const float *
 SINCOS_API int sinusoid_f32_forward(const float *t, int64_t N, const float *A, const float *w,
                          const float *phi, int32_t K, float *y, void *stream);
 
+/* The forward model fused with the residual and the loss of a least-squares
+ * fit (Sec. II's use of the smooth pair):  r_i = y_i - y_obs_i in binary32,
+ * with y_i exactly as sinusoid_f32_forward computes it, written to r; and
+ * loss[0] = 1/2 sum_i r_i^2, summed in a fixed order (per lane with fma in
+ * sample order, a 256-way tree per workgroup, then a tree over the
+ * workgroups), so the result is deterministic.
+ * t, y_obs, r: [N] device arrays; r may be t or y_obs exactly (no other
+ * overlap).  loss: one device float (written also when N == 0, as +0).
+ * workspace: device scratch of at least
+ * sinusoid_f32_residual_workspace_bytes(N) bytes (one float per workgroup,
+ * 4 ceil(N / 2048) bytes up to 4 MiB), owned by the caller.              */
+SINCOS_API int64_t sinusoid_f32_residual_workspace_bytes(int64_t N);
+SINCOS_API int sinusoid_f32_residual(const float *t, const float *y_obs, int64_t N, const float *A,
+                                     const float *w, const float *phi, int32_t K, float *r,
+                                     float *loss, void *workspace, int64_t workspace_bytes,
+                                     void *stream);
+
 /* Gradients of a loss L with dL/dy_i = g_i:
  *     gA_k   = sum_i g_i s_ik
  *     gphi_k = A_k sum_i g_i c_ik

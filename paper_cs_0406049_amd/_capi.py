@@ -90,6 +90,9 @@ _SIGNATURES = {
     "sincos_f32_backward": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P]),
     "sinusoid_f32_forward": (ctypes.c_int, [_P, _I64, _P, _P, _P, _I32, _P, _P]),
     "sinusoid_f32_backward_workspace_bytes": (ctypes.c_int64, [_I64, _I32]),
+    "sinusoid_f32_residual_workspace_bytes": (ctypes.c_int64, [_I64]),
+    "sinusoid_f32_residual": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _P, _P, _P, _I64,
+                                             _P]),
     "sinusoid_f32_backward": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _P, _P, _P, _P, _I64,
                                              _P]),
     "sincos_copy_ceiling_f32": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(Launch), _P]),
@@ -320,6 +323,22 @@ def sinusoid_f32_forward(t, A, w, phi, y, N=None, K=None, stream=None) -> None:
     N, K = _numel(t, N), _numel(A, K)
     _check(lib().sinusoid_f32_forward(_ptr(t, N), N, _ptr(A, K), _ptr(w, K), _ptr(phi, K), K,
                                       _ptr(y, N), _stream(stream)))
+
+
+def sinusoid_f32_residual_workspace_bytes(N: int) -> int:
+    return int(lib().sinusoid_f32_residual_workspace_bytes(int(N)))
+
+
+def sinusoid_f32_residual(t, y_obs, A, w, phi, r, loss, workspace, workspace_bytes=None, N=None,
+                          K=None, stream=None) -> None:
+    """r = model(t) - y_obs and loss[0] = 1/2 sum r^2 (deterministic order)."""
+    N, K = _numel(t, N), _numel(A, K)
+    if workspace_bytes is None:
+        workspace_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _check(lib().sinusoid_f32_residual(_ptr(t, N), _ptr(y_obs, N), N, _ptr(A, K), _ptr(w, K),
+                                       _ptr(phi, K), K, _ptr(r, N), _ptr(loss, 1),
+                                       _raw_ptr(workspace, int(workspace_bytes)),
+                                       int(workspace_bytes), _stream(stream)))
 
 
 def sinusoid_f32_backward_workspace_bytes(N: int, K: int) -> int:

@@ -84,16 +84,17 @@ def sinusoid(t, A, w, phi):
 
 def sinusoid_loss_and_grads(t, y_obs, A, w, phi):
     """L = 1/2 sum (y - y_obs)^2 and (dL/dA, dL/dw, dL/dphi) via the kernels,
-    without autograd bookkeeping: forward kernel, one residual subtraction,
-    adjoint kernel."""
+    without autograd bookkeeping: the forward kernel fused with the residual
+    and the loss, then the adjoint kernel.  L is a 0-dim float32 tensor."""
     N, K = t.numel(), A.numel()
-    y = torch.empty_like(t)
-    _capi.sinusoid_f32_forward(t, A, w, phi, y, N, K)
-    r = y - y_obs
+    r = torch.empty_like(t)
+    loss = torch.empty(1, dtype=torch.float32, device=t.device)
     gA = torch.empty_like(A)
     gw = torch.empty_like(w)
     gphi = torch.empty_like(phi)
-    nbytes = _capi.sinusoid_f32_backward_workspace_bytes(N, K)
-    ws = torch.empty(max(nbytes, 4), dtype=torch.uint8, device=t.device)
-    _capi.sinusoid_f32_backward(t, r, A, w, phi, gA, gw, gphi, ws, nbytes, N, K)
-    return 0.5 * torch.dot(r, r), gA, gw, gphi
+    nb_fwd = _capi.sinusoid_f32_residual_workspace_bytes(N)
+    nb_adj = _capi.sinusoid_f32_backward_workspace_bytes(N, K)
+    ws = torch.empty(max(nb_fwd, nb_adj, 4), dtype=torch.uint8, device=t.device)
+    _capi.sinusoid_f32_residual(t, y_obs, A, w, phi, r, loss, ws, nb_fwd, N, K)
+    _capi.sinusoid_f32_backward(t, r, A, w, phi, gA, gw, gphi, ws, nb_adj, N, K)
+    return loss[0], gA, gw, gphi

@@ -721,6 +721,48 @@ extern "C" int sinusoid_f32_forward(const float *t, int64_t N, const float *A, c
     return e == hipSuccess ? SINCOS_OK : hip_error(e, "sinusoid_f32_forward: kernel launch");
 }
 
+extern "C" int64_t sinusoid_f32_residual_workspace_bytes(int64_t N)
+{
+    if (N < 0)
+        return -1;
+    return sinusoid_fwd_blocks(N) * (int64_t)sizeof(float);
+}
+
+extern "C" int sinusoid_f32_residual(const float *t, const float *y_obs, int64_t N, const float *A,
+                                     const float *w, const float *phi, int32_t K, float *r,
+                                     float *loss, void *workspace, int64_t workspace_bytes,
+                                     void *stream)
+{
+    clear_error();
+    if (N < 0)
+        return set_error(SINCOS_EINVAL, "sinusoid_f32_residual: N < 0");
+    int rc = check_params(A, w, phi, K, "sinusoid_f32_residual");
+    if (rc != SINCOS_OK)
+        return rc;
+    if (!loss)
+        return set_error(SINCOS_EINVAL, "sinusoid_f32_residual: null loss");
+    if (N > 0) {
+        if (!t || !y_obs || !r)
+            return set_error(SINCOS_EINVAL, "sinusoid_f32_residual: null t, y_obs or r with N > 0");
+        if (!aligned4(t) || !aligned4(y_obs) || !aligned4(r) || !aligned4(loss))
+            return set_error(SINCOS_EINVAL, "sinusoid_f32_residual: pointers must be 4-byte aligned");
+        if ((r != t && ranges_overlap(r, N, t, N)) || (r != y_obs && ranges_overlap(r, N, y_obs, N)))
+            return set_error(SINCOS_EOVERLAP, "sinusoid_f32_residual: r partially overlaps t or y_obs");
+        if (ranges_overlap(loss, 1, r, N))
+            return set_error(SINCOS_EOVERLAP, "sinusoid_f32_residual: loss overlaps r");
+        const int64_t need = sinusoid_f32_residual_workspace_bytes(N);
+        if (!workspace || workspace_bytes < need)
+            return set_error(SINCOS_EINVAL, "sinusoid_f32_residual: workspace needs " +
+                                                std::to_string(need) + " bytes");
+    }
+    const DeviceInfo *dev;
+    if ((rc = current_device(&dev)) != SINCOS_OK)
+        return rc;
+    hipError_t e = launch_sinusoid_residual(t, y_obs, N, A, w, phi, K, r, loss,
+                                            static_cast<float *>(workspace), (hipStream_t)stream);
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "sinusoid_f32_residual: kernel launch");
+}
+
 extern "C" int64_t sinusoid_f32_backward_workspace_bytes(int64_t N, int32_t K)
 {
     if (N < 0 || K < 0)

@@ -195,17 +195,24 @@ __global__ void __launch_bounds__(256) k_backward_scalar(const float *s, const f
 // sum order is k = 0..K-1 exactly; A_k, w_k, phi_k are wave-uniform (scalar
 // loads).  Only the sine of each pair is used; the cosine-only operations
 // are dropped by the compiler.
+// RESID: write the residual r_i = y_i - y_obs_i instead of y_i, and the
+// workgroup's sum of r_i^2 to loss_part[blockIdx.x]: each lane adds its r^2
+// with fma in sample order, then a fixed 256-way tree in LDS.
 
 constexpr int kFwdIPT = 8;
+constexpr int kFwdBlock = 256;
 
-__global__ void __launch_bounds__(256) k_sinusoid_fwd(const float *t, int64_t N,
-                                                      const float *__restrict__ A,
-                                                      const float *__restrict__ w,
-                                                      const float *__restrict__ phi, int32_t K,
-                                                      float *y)
+template <bool RESID>
+__global__ void __launch_bounds__(kFwdBlock) k_sinusoid_fwd(const float *t, int64_t N,
+                                                            const float *__restrict__ A,
+                                                            const float *__restrict__ w,
+                                                            const float *__restrict__ phi,
+                                                            int32_t K, float *y,
+                                                            const float *y_obs, float *loss_part)
 {
     const int64_t bd = blockDim.x;
     const int64_t stride = (int64_t)gridDim.x * bd * kFwdIPT;
+    float sq = 0.0f;
     for (int64_t base = (int64_t)blockIdx.x * bd * kFwdIPT + threadIdx.x; base < N;
          base += stride) {
         float ti[kFwdIPT], acc[kFwdIPT];
@@ -228,10 +235,47 @@ __global__ void __launch_bounds__(256) k_sinusoid_fwd(const float *t, int64_t N,
 #pragma unroll
         for (int r = 0; r < kFwdIPT; ++r) {
             const int64_t i = base + r * bd;
-            if (i < N)
-                y[i] = acc[r];
+            if (i < N) {
+                float v = acc[r];
+                if (RESID) {
+                    v = v - y_obs[i];
+                    sq = __builtin_fmaf(v, v, sq);
+                }
+                y[i] = v;
+            }
         }
     }
+    if (RESID) {
+        __shared__ float red[kFwdBlock];
+        red[threadIdx.x] = sq;
+        __syncthreads();
+        for (int h = kFwdBlock / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h)
+                red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0)
+            loss_part[blockIdx.x] = red[0];
+    }
+}
+
+// loss = 1/2 * (sum of the workgroup partials): one workgroup, strided
+// per-thread sums, then a fixed 256-way tree.
+__global__ void __launch_bounds__(256) k_loss_reduce(const float *part, int64_t nparts, float *loss)
+{
+    __shared__ float red[256];
+    float acc = 0.0f;
+    for (int64_t j = threadIdx.x; j < nparts; j += 256)
+        acc += part[j];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        loss[0] = 0.5f * red[0];
 }
 
 // K5: sinusoid adjoint.  Lane <-> frequency k (a wave covers 64 of them),
@@ -574,16 +618,36 @@ hipError_t launch_backward(const float *s, const float *c, const float *gs, cons
     return hipGetLastError();
 }
 
+int64_t sinusoid_fwd_blocks(int64_t N)
+{
+    // one tile of samples per workgroup; the kernel's grid-stride loop covers
+    // any N beyond 2^20 workgroups
+    const int64_t per_block = (int64_t)kFwdBlock * kFwdIPT;
+    return std::max<int64_t>(1, std::min<int64_t>((N + per_block - 1) / per_block, int64_t(1) << 20));
+}
+
 hipError_t launch_sinusoid_forward(const float *t, int64_t N, const float *A, const float *w,
                                    const float *phi, int32_t K, float *y, hipStream_t st)
 {
-    const int64_t per_block = 256 * kFwdIPT;
-    // one tile of samples per workgroup; the kernel's grid-stride loop covers
-    // any N beyond 2^20 workgroups
-    const int64_t grid =
-        std::max<int64_t>(1, std::min<int64_t>((N + per_block - 1) / per_block, int64_t(1) << 20));
-    hipLaunchKernelGGL(k_sinusoid_fwd, dim3((unsigned)grid), dim3(256), 0, st, t, N, A, w, phi, K,
-                       y);
+    const int64_t grid = sinusoid_fwd_blocks(N);
+    hipLaunchKernelGGL(k_sinusoid_fwd<false>, dim3((unsigned)grid), dim3(kFwdBlock), 0, st, t, N,
+                       A, w, phi, K, y, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_sinusoid_residual(const float *t, const float *y_obs, int64_t N, const float *A,
+                                    const float *w, const float *phi, int32_t K, float *r,
+                                    float *loss, float *part, hipStream_t st)
+{
+    const int64_t grid = sinusoid_fwd_blocks(N);
+    if (N > 0) {
+        hipLaunchKernelGGL(k_sinusoid_fwd<true>, dim3((unsigned)grid), dim3(kFwdBlock), 0, st, t,
+                           N, A, w, phi, K, r, y_obs, part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, st, part, N > 0 ? grid : 0, loss);
     return hipGetLastError();
 }
 

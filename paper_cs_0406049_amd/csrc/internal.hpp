@@ -67,6 +67,10 @@ hipError_t launch_backward(const float *s, const float *c, const float *gs, cons
                            float *gx, int64_t n, hipStream_t stream);
 hipError_t launch_sinusoid_forward(const float *t, int64_t N, const float *A, const float *w,
                                    const float *phi, int32_t K, float *y, hipStream_t stream);
+int64_t sinusoid_fwd_blocks(int64_t N);
+hipError_t launch_sinusoid_residual(const float *t, const float *y_obs, int64_t N, const float *A,
+                                    const float *w, const float *phi, int32_t K, float *r,
+                                    float *loss, float *part, hipStream_t stream);
 hipError_t launch_huygens(const float *xo, const float *yo, int64_t P, const float *src,
                           int32_t S, float k, float L, float *re, float *im, hipStream_t stream);
 int64_t sinusoid_chunks(int64_t N);

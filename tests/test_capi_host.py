@@ -155,6 +155,25 @@ def test_sinusoid_validation_and_workspace(L):
     assert rc == _capi.EINVAL and "workspace" in _capi.last_error()
 
 
+def test_sinusoid_residual_validation(L):
+    f = L.sinusoid_f32_residual
+    wb = L.sinusoid_f32_residual_workspace_bytes
+    assert wb(-1) == -1
+    assert wb(4_194_304) == 2048 * 4               # one float per 2048-sample workgroup
+    assert wb(1) == 4 and wb(0) == 4
+    assert wb(1 << 40) == (1 << 20) * 4            # the grid is capped; the kernel strides
+    t, yo, r, loss, ws = BASE, BASE + 65536, BASE + 2 * 65536, BASE + 3 * 65536, BASE + 4 * 65536
+    prm = (BASE + 5 * 65536,) * 3
+    assert f(t, yo, -1, *prm, 4, r, loss, ws, 64, None) == _capi.EINVAL
+    assert f(t, yo, 16, *prm, 4, r, None, ws, 64, None) == _capi.EINVAL          # null loss
+    assert f(t, None, 16, *prm, 4, r, loss, ws, 64, None) == _capi.EINVAL        # null y_obs
+    assert f(t, yo, 16, *prm, 4, t + 4, loss, ws, 64, None) == _capi.EOVERLAP    # r partly t
+    assert f(t, yo, 16, *prm, 4, r, r + 8, ws, 64, None) == _capi.EOVERLAP       # loss inside r
+    rc = f(t, yo, 16, *prm, 4, r, loss, ws, 0, None)
+    assert rc == _capi.EINVAL and "workspace" in _capi.last_error()
+    assert f(t, yo, 16, None, None, None, 4, r, loss, ws, 64, None) == _capi.EINVAL
+
+
 def test_copy_ceiling_validation(L):
     f = L.sincos_copy_ceiling_f32
     assert f(BASE, BASE + 4096, BASE + 8192, 6, None, None) == _capi.EINVAL

@@ -322,6 +322,49 @@ def test_sinusoid_forward_bit_exact_and_adjoint_bound(torch_dev, N, K):
         assert np.all(err <= bound), (key, (err / np.maximum(bound, 1e-300)).max())
 
 
+@pytest.mark.parametrize("N,K", [(1, 1), (1000, 3), (4099, 64), (300000, 64), (2049, 0)])
+def test_sinusoid_residual_and_loss(torch_dev, N, K):
+    """r = y - y_obs bit-exact (y as the oracle's forward), the loss within the
+    rounding bound of its fixed-order binary32 sums; in place over y_obs too."""
+    torch = torch_dev
+    from paper_cs_0406049_amd import _capi
+    t, A, w, phi = _sinusoid_small(N, K, 7 * N + K)
+    yobs = np.random.default_rng(N).standard_normal(N).astype(np.float32)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    td, Ad, wd, pd, yd = d(t), d(A), d(w), d(phi), d(yobs)
+    nb = _capi.sinusoid_f32_residual_workspace_bytes(N)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    r = torch.empty_like(td)
+    loss = torch.empty(1, device="cuda")
+    _capi.sinusoid_f32_residual(td, yd, Ad, wd, pd, r, loss, ws, nb, N, K)
+    torch.cuda.synchronize()
+    y_or = oracle.sinusoid_forward(t, A, w, phi, threads=oracle.default_threads()) if K else \
+        np.zeros(N, np.float32)
+    r_or = (y_or - yobs).astype(np.float32)
+    assert_bit_exact(r.cpu().numpy(), r_or, "residual N=%d K=%d" % (N, K))
+    sq = r_or.astype(np.float64) ** 2
+    exact = 0.5 * float(sq.sum())
+    blocks = _capi.sinusoid_f32_residual_workspace_bytes(N) // 4
+    depth = 8 + 8 + -(-blocks // 256) + 8 + 2
+    assert abs(float(loss.cpu()[0]) - exact) <= depth * U * 0.5 * float(sq.sum()) * 1.001
+    # in place: r over y_obs
+    yd2 = d(yobs)
+    _capi.sinusoid_f32_residual(td, yd2, Ad, wd, pd, yd2, loss, ws, nb, N, K)
+    torch.cuda.synchronize()
+    assert_bit_exact(yd2.cpu().numpy(), r_or, "residual in place N=%d" % N)
+
+
+def test_sinusoid_residual_empty(torch_dev):
+    torch = torch_dev
+    from paper_cs_0406049_amd import _capi
+    A = torch.ones(3, device="cuda")
+    loss = torch.full((1,), 7.0, device="cuda")
+    ws = torch.empty(4, dtype=torch.uint8, device="cuda")
+    _capi.sinusoid_f32_residual(0, 0, A, A, A, 0, loss, ws, 4, N=0, K=3)
+    torch.cuda.synchronize()
+    assert float(loss.cpu()[0]) == 0.0
+
+
 def test_sinusoid_deterministic(torch_dev):
     torch = torch_dev
     from paper_cs_0406049_amd.autograd import sinusoid_loss_and_grads
