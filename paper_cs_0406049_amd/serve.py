@@ -39,8 +39,8 @@ class Server:
 
     def submit(self, x, n=None, tag: int = 0) -> int:
         """Queue sin/cos of x (a device tensor or address); returns the id."""
-        ptr = x if isinstance(x, int) else _capi._ptr(x)
         n = int(n if n is not None else x.numel())
+        ptr = x if isinstance(x, int) else _capi._ptr(x, n)
         rid = ctypes.c_int64()
         _capi._check(_capi.lib().sincos_server_submit(self._h, ptr, n, int(tag), ctypes.byref(rid)))
         return rid.value
@@ -64,6 +64,8 @@ class Server:
         """Submit request j (input address xs[j], ns[j] elements) at
         arrival_ns[j] after the start; wait for all; completions by index."""
         count = len(ns)
+        if len(xs) != count or len(arrival_ns) != count:
+            raise ValueError("xs, ns and arrival_ns must have the same length")
         xa = (ctypes.c_void_p * max(count, 1))(*[int(v) for v in xs])
         na = np.ascontiguousarray(ns, np.int64)
         aa = np.ascontiguousarray(arrival_ns, np.int64)

@@ -193,3 +193,9 @@ def test_autotune_cache_keys_and_candidates(tmp_path):
     autotune.save_cache({k1: {"shape": [256, 4, 2048]}}, p)
     assert autotune.load_cache(p)[k1]["shape"] == [256, 4, 2048]
     assert autotune.load_cache(str(tmp_path / "missing.json")) == {}
+
+
+def test_replay_rejects_mismatched_tables():
+    with sim(auto_release=True) as s:
+        with pytest.raises(ValueError):
+            s.replay([FAKE] * 3, np.full(4, 100, np.int64), np.zeros(4, np.int64))
