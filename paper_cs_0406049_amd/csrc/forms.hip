@@ -120,8 +120,9 @@ __global__ void __launch_bounds__(1024) k_ragged(const RaggedDesc *__restrict__ 
             const f4 *xv = reinterpret_cast<const f4 *>(d.x + d.head);
             f4 *sv = reinterpret_cast<f4 *>(d.s + d.head);
             f4 *cv = reinterpret_cast<f4 *>(d.c + d.head);
-            // global non-temporal loads and stores: measured 15 % faster here
-            // than the plain kernel's buffer-instruction tile
+            // global non-temporal loads and stores: over thousands of separate
+            // arrays the plain kernel's sc1 store policy measured 12 % slower
+            // (buffer or global loads, nt stores: the same rate)
             stream_vec_tile<A, M, U>(xv, sv, cv, local * bd * U + threadIdx.x, d.n4, bd);
         } else {
             stream_scalar_tile<A, M, U>(d.x, d.s, d.c, local * bd * U * 4 + threadIdx.x, d.n, bd);
