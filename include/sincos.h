@@ -210,9 +210,9 @@ SINCOS_API int sinusoid_f32_residual(const float *t, const float *y_obs, int64_t
  * in binary32 per block of samples and combined in a fixed order, so the
  * result is deterministic.  gA, gw, gphi: [K] device outputs.  workspace:
  * device scratch of at least sinusoid_f32_backward_workspace_bytes(N, K)
- * bytes (3 * 64 ceil(K/64) ceil(N/8192) floats: one partial per 8192
+ * bytes (3 * 64 ceil(K/64) ceil(N/2048) floats: one partial per 2048
  * samples and frequency), owned by the caller, not aliasing anything else.
- * EINVAL if N > 2^31 * 8192.                                              */
+ * EINVAL if N > 2^31 * 2048.                                              */
 SINCOS_API int64_t sinusoid_f32_backward_workspace_bytes(int64_t N, int32_t K);
 SINCOS_API int sinusoid_f32_backward(const float *t, const float *g, int64_t N, const float *A,
                           const float *w, const float *phi, int32_t K, float *gA, float *gw,

@@ -144,10 +144,10 @@ def test_sinusoid_validation_and_workspace(L):
     assert L.sinusoid_f32_forward(None, 0, BASE, BASE, BASE, 3, None, None) == _capi.OK
     wb = L.sinusoid_f32_backward_workspace_bytes
     assert wb(-1, 4) == -1
-    assert wb(4_194_304, 64) == 512 * 3 * 64 * 4       # one partial per 8192 samples and lane
+    assert wb(4_194_304, 64) == 2048 * 3 * 64 * 4      # one partial per 2048 samples and lane
     assert wb(1025, 65) == 1 * 3 * 128 * 4
-    assert wb(8193, 1) == 2 * 3 * 64 * 4
-    rc = L.sinusoid_f32_backward(BASE, BASE, (1 << 31) * 8192 + 1, BASE, BASE, BASE, 4, BASE, BASE,
+    assert wb(8193, 1) == 5 * 3 * 64 * 4
+    rc = L.sinusoid_f32_backward(BASE, BASE, (1 << 31) * 2048 + 1, BASE, BASE, BASE, 4, BASE, BASE,
                                  BASE, BASE, 1 << 40, None)
     assert rc == _capi.EINVAL and "too large" in _capi.last_error()
     rc = L.sinusoid_f32_backward(BASE, BASE + 4096, 4096, BASE + 8192, BASE + 8192, BASE + 8192, 64,

@@ -280,7 +280,7 @@ def _sinusoid_small(N, K, seed):
     return t, A, w, phi
 
 
-ADJ_CHUNK = 512   # samples per wave in the adjoint kernel
+ADJ_CHUNK = 128   # samples per wave in the adjoint kernel
 ADJ_WAVES = 16    # waves per workgroup, summed in a pairwise tree
 
 
