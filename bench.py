@@ -107,8 +107,22 @@ def cpu_baseline(x_host, arith: int):
     t0 = time.perf_counter()
     oracle.sincos(x_host[:m], arith, 0, threads=1)
     dt1 = time.perf_counter() - t0
+    from paper_cs_0406049_amd import workloads
+    small = workloads.plain_small()   # the 1,048,576-angle small workload, best of 5
+    small_dt = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        oracle.sincos(small, arith, 0, threads=threads)
+        small_dt.append(time.perf_counter() - t0)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": x_host.size / dt / 1e9, "unit": "Gelem/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model, "nproc": os.cpu_count(),
+            "small_workload_value": round(small.size / min(small_dt) / 1e9, 5),
             "sample": "the full %d-element array, median of 3 passes, %s arithmetic, %d threads "
                       "over contiguous chunks (%.2f s wall per pass, %.1f thread-seconds in all); "
                       "single thread on its first %d elements: %.4f Gelem/s"
