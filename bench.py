@@ -176,6 +176,21 @@ def bench_ragged(torch, reps, plain_gbs):
             "speedup_vs_per_array": round(pa_ms / g_ms, 2)}
 
 
+def bench_variants(torch, reps, plain_gbs, x, s, c):
+    """The plain kernel with the other arithmetics and the second method, over
+    the same roofline arrays (all HBM-bound: the same 12 bytes per element)."""
+    from paper_cs_0406049_amd import _capi
+    n = x.numel()
+    res = {"workload": "the roofline workload (%d angles), plain form" % n}
+    for name, arith, method in (("fused_method2", 0, 1), ("split_method1", 1, 0),
+                                ("split_method2", 1, 1), ("contract_method1", 2, 0)):
+        ms, _ = time_launches(torch, lambda: _capi.sincos_f32_ex(x, s, c, n, arith, method), reps, 3)
+        gbs = BYTES_PER_ELEM * n / (ms * 1e-3) / 1e9
+        res[name] = {"kernel_ms": round(ms, 4), "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+                     "GBps": round(gbs, 1), "per_byte_vs_plain": round(gbs / plain_gbs, 4)}
+    return res
+
+
 def bench_adjoint(torch, reps, plain_gbs):
     """Elementwise adjoint gx = gs*c - gc*s over the roofline size: 16 bytes
     read and 4 written per element, against the plain kernel's per-byte rate."""
@@ -375,7 +390,8 @@ def main(argv=None):
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceiling", action="store_true")
-    ap.add_argument("--forms", default="ragged,interleaved,adjoint,sinusoid,huygens,serve",
+    ap.add_argument("--forms",
+                    default="variants,ragged,interleaved,adjoint,sinusoid,huygens,serve",
                     help="comma list of forms to measure after the plain kernel ('' = none)")
     args = ap.parse_args(argv)
 
@@ -485,10 +501,16 @@ def main(argv=None):
         out["cpu_baseline"] = cpu_baseline(x_host, arith)
     forms = [f for f in args.forms.split(",") if f]
     if forms:
+        out["forms"] = {}
+        if "variants" in forms:  # uses the roofline arrays, so before they are freed
+            log("form: variants")
+            out["forms"]["variants"] = bench_variants(torch, max(10, args.steps // 4), achieved,
+                                                      x, s, c)
         del x, s, c
         torch.cuda.empty_cache()
-        out["forms"] = {}
     for f in forms:
+        if f == "variants":
+            continue
         log("form: %s" % f)
         if f == "ragged":
             out["forms"]["ragged"] = bench_ragged(torch, max(5, args.steps // 4), achieved)
