@@ -61,6 +61,41 @@ def test_plain_and_backward_in_a_captured_graph(torch_dev):
         assert_bit_exact(gx.cpu().numpy(), oracle.sincos_backward(so, co, gsh, gch), "replay %d gx" % rep)
 
 
+def test_fit_step_in_a_captured_graph(torch_dev):
+    """One least-squares fit step (fused residual and loss, adjoint with its
+    reduction) captured as a graph: no allocation or synchronization happens
+    inside the library calls, and the kernels sum in a fixed order, so every
+    replay gives the same bits as the eager call on the same inputs."""
+    torch = torch_dev
+    from paper_cs_0406049_amd import workloads
+    from paper_cs_0406049_amd.autograd import sinusoid_loss_and_grads
+    p = workloads.sinusoid_problem(N=300_000, K=64)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()  # noqa: E731
+    t, yobs, A, w, phi = d(p.t), d(p.y_obs), d(p.A), d(p.w), d(p.phi)
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):        # warm-up outside capture
+        sinusoid_loss_and_grads(t, yobs, A, w, phi)
+    torch.cuda.current_stream().wait_stream(st)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        out = sinusoid_loss_and_grads(t, yobs, A, w, phi)
+    for rep in range(3):
+        rng = np.random.default_rng(100 + rep)
+        A.copy_(d(p.A + 0.01 * rng.standard_normal(p.A.size)))
+        phi.copy_(d(p.phi + 0.01 * rng.standard_normal(p.phi.size)))
+        _ = (torch.randn(1 << 18, device="cuda") * 2).sum()       # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = [o.detach().clone() for o in out]
+        want = sinusoid_loss_and_grads(t, yobs, A, w, phi)
+        torch.cuda.synchronize()
+        for k, (a, b) in enumerate(zip(got, want)):
+            assert torch.equal(a.view(torch.int32), b.view(torch.int32)), (rep, k)
+
+
 def test_ragged_from_many_threads_on_their_own_streams(torch_dev):
     """Several host threads enqueue one-shot ragged batches (sharing the
     library's staging ring) on their own streams at the same time."""
