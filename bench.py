@@ -176,18 +176,28 @@ def bench_ragged(torch, reps, plain_gbs):
             "speedup_vs_per_array": round(pa_ms / g_ms, 2)}
 
 
-def bench_variants(torch, reps, plain_gbs, x, s, c):
+def bench_variants(torch, reps, x, s, c):
     """The plain kernel with the other arithmetics and the second method, over
     the same roofline arrays (all HBM-bound: the same 12 bytes per element)."""
+    import numpy as np
     from paper_cs_0406049_amd import _capi
     n = x.numel()
-    res = {"workload": "the roofline workload (%d angles), plain form" % n}
-    for name, arith, method in (("fused_method2", 0, 1), ("split_method1", 1, 0),
-                                ("split_method2", 1, 1), ("contract_method1", 2, 0)):
-        ms, _ = time_launches(torch, lambda: _capi.sincos_f32_ex(x, s, c, n, arith, method), reps, 3)
+    res = {"workload": "the roofline workload (%d angles), plain form; A/B rounds against "
+                       "the default (fused, first method), median of 3" % n}
+    cases = (("fused_method1", 0, 0), ("fused_method2", 0, 1), ("split_method1", 1, 0),
+             ("split_method2", 1, 1), ("contract_method1", 2, 0))
+    times = {name: [] for name, _, _ in cases}
+    for _ in range(3):         # interleaved rounds, so a slow spell hits every case alike
+        for name, arith, method in cases:
+            ms, _ = time_launches(
+                torch, lambda: _capi.sincos_f32_ex(x, s, c, n, arith, method), reps, 3)
+            times[name].append(ms)
+    base = float(np.median(times["fused_method1"]))
+    for name, _, _ in cases[1:]:
+        ms = float(np.median(times[name]))
         gbs = BYTES_PER_ELEM * n / (ms * 1e-3) / 1e9
         res[name] = {"kernel_ms": round(ms, 4), "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
-                     "GBps": round(gbs, 1), "per_byte_vs_plain": round(gbs / plain_gbs, 4)}
+                     "GBps": round(gbs, 1), "per_byte_vs_plain": round(base / ms, 4)}
     return res
 
 
@@ -517,8 +527,7 @@ def main(argv=None):
         out["forms"] = {}
         if "variants" in forms:  # uses the roofline arrays, so before they are freed
             log("form: variants")
-            out["forms"]["variants"] = bench_variants(torch, max(10, args.steps // 4), achieved,
-                                                      x, s, c)
+            out["forms"]["variants"] = bench_variants(torch, max(10, args.steps // 4), x, s, c)
         del x, s, c
         torch.cuda.empty_cache()
     for f in forms:

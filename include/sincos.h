@@ -153,7 +153,8 @@ typedef struct sincos_ragged_plan sincos_ragged_plan_t;
 SINCOS_API int sincos_ragged_plan_create(const sincos_seg_t *segs, const int64_t *lens, int32_t count,
                               int32_t arith, int32_t method, const sincos_launch_t *launch,
                               sincos_ragged_plan_t **out_plan);
-/* Enqueue the plan's kernel on `stream`. */
+/* Enqueue the plan's kernel on `stream`.  Both launch calls need the
+ * plan's device to be current (EINVAL otherwise).                         */
 SINCOS_API int sincos_ragged_plan_launch(const sincos_ragged_plan_t *plan, void *stream);
 /* Enqueue the plan as a HIP graph (built by stream capture of the kernel on
  * the first call and instantiated once; later calls replay it).          */
@@ -181,7 +182,9 @@ SINCOS_API int sincos_f32_backward(const float *s, const float *c, const float *
  * In binary32: theta_ik = fma(w_k, t_i, phi_k); y_i accumulates
  * fma(A_k, s_ik, y_i) over k = 0..K-1 in order, starting from +0.  Uses
  * FUSED arithmetic and the NORMALIZED method for the pair.
- * t, y: [N] device arrays; A, w, phi: [K] device arrays.  K >= 0.         */
+ * t, y: [N] device arrays; A, w, phi: [K] device arrays; all 4-byte
+ * aligned.  K >= 0.  y may be t exactly; any other overlap of y with t, A,
+ * w or phi is EOVERLAP.                                                   */
 SINCOS_API int sinusoid_f32_forward(const float *t, int64_t N, const float *A, const float *w,
                          const float *phi, int32_t K, float *y, void *stream);
 
@@ -195,7 +198,9 @@ SINCOS_API int sinusoid_f32_forward(const float *t, int64_t N, const float *A, c
  * overlap).  loss: one device float (written also when N == 0, as +0).
  * workspace: device scratch of at least
  * sinusoid_f32_residual_workspace_bytes(N) bytes (one float per workgroup,
- * 4 ceil(N / 2048) bytes up to 4 MiB), owned by the caller.              */
+ * 4 ceil(N / 2048) bytes up to 4 MiB), owned by the caller.  r, loss and
+ * the workspace's used bytes overlap neither each other nor t, y_obs, A, w,
+ * phi (EOVERLAP), apart from the exact in-place r; all 4-byte aligned.    */
 SINCOS_API int64_t sinusoid_f32_residual_workspace_bytes(int64_t N);
 SINCOS_API int sinusoid_f32_residual(const float *t, const float *y_obs, int64_t N, const float *A,
                                      const float *w, const float *phi, int32_t K, float *r,
@@ -211,8 +216,9 @@ SINCOS_API int sinusoid_f32_residual(const float *t, const float *y_obs, int64_t
  * result is deterministic.  gA, gw, gphi: [K] device outputs.  workspace:
  * device scratch of at least sinusoid_f32_backward_workspace_bytes(N, K)
  * bytes (3 * 64 ceil(K/64) ceil(N/2048) floats: one partial per 2048
- * samples and frequency), owned by the caller, not aliasing anything else.
- * EINVAL if N > 2^31 * 2048.                                              */
+ * samples and frequency), owned by the caller.  gA, gw, gphi and the
+ * workspace's used bytes overlap neither each other nor t, g, A, w, phi
+ * (EOVERLAP); all arrays 4-byte aligned.  EINVAL if N > 2^31 * 2048.      */
 SINCOS_API int64_t sinusoid_f32_backward_workspace_bytes(int64_t N, int32_t K);
 SINCOS_API int sinusoid_f32_backward(const float *t, const float *g, int64_t N, const float *A,
                           const float *w, const float *phi, int32_t K, float *gA, float *gw,

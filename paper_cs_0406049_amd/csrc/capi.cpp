@@ -8,6 +8,7 @@
 #include <climits>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -118,6 +119,49 @@ static bool ranges_overlap(const void *a, int64_t na, const void *b, int64_t nb)
 }
 
 static bool aligned4(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 3) == 0; }
+
+// A device array of n floats, named for error messages (n <= 0 or a null
+// pointer: nothing to check).
+struct Span {
+    const void *p;
+    int64_t n;
+    const char *name;
+};
+
+// Every output span disjoint from every input span and from the other
+// outputs; `same_ok` lets an output equal one input exactly (in place).
+static int check_disjoint(std::initializer_list<Span> outs, std::initializer_list<Span> ins,
+                          const char *who, const void *same_ok_out = nullptr,
+                          const void *same_ok_in_a = nullptr, const void *same_ok_in_b = nullptr)
+{
+    auto live = [](const Span &a) { return a.p && a.n > 0; };
+    for (auto o = outs.begin(); o != outs.end(); ++o) {
+        if (!live(*o))
+            continue;
+        for (auto q = o + 1; q != outs.end(); ++q)
+            if (live(*q) && ranges_overlap(o->p, o->n, q->p, q->n))
+                return set_error(SINCOS_EOVERLAP, std::string(who) + ": " + o->name + " overlaps " +
+                                                      q->name);
+        for (const Span &in : ins) {
+            if (!live(in) || !ranges_overlap(o->p, o->n, in.p, in.n))
+                continue;
+            const bool in_place = o->p == same_ok_out && in.p == o->p && in.n == o->n &&
+                                  (in.p == same_ok_in_a || in.p == same_ok_in_b);
+            if (!in_place)
+                return set_error(SINCOS_EOVERLAP, std::string(who) + ": " + o->name + " overlaps " +
+                                                      in.name);
+        }
+    }
+    return SINCOS_OK;
+}
+
+static bool all_aligned4(std::initializer_list<const void *> ps)
+{
+    for (const void *p : ps)
+        if (p && !aligned4(p))
+            return false;
+    return true;
+}
 
 static int check_triplet(const float *x, const float *s, const float *c, int64_t n,
                          const char *who)
@@ -350,14 +394,11 @@ int ragged_enqueue(const RaggedTable &t, int arith, int method, const LaunchShap
     e = hipEventRecord(slot.done, stream);
     if (e == hipSuccess)
         slot.pending = true;
+    else
+        (void)hipStreamSynchronize(stream);  // the slot cannot be proven idle: drain instead
     if (rc != SINCOS_OK)
         return rc;
-    if (e != hipSuccess) {
-        // the slot cannot be proven idle any more: wait for the stream instead
-        (void)hipStreamSynchronize(stream);
-        return hip_error(e, "ragged: event record");
-    }
-    return SINCOS_OK;
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "ragged: event record");
 }
 
 }  // namespace mi355
@@ -575,6 +616,20 @@ extern "C" int sincos_ragged_plan_create(const sincos_seg_t *segs, const int64_t
     return SINCOS_OK;
 }
 
+// Plans hold device addresses of the device they were made on.
+static int check_plan_device(const sincos_ragged_plan *plan, const char *who)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_error(e, who);
+    if (dev != plan->device)
+        return set_error(SINCOS_EINVAL, std::string(who) + ": plan made on device " +
+                                            std::to_string(plan->device) + ", current device is " +
+                                            std::to_string(dev));
+    return SINCOS_OK;
+}
+
 extern "C" int sincos_ragged_plan_launch(const sincos_ragged_plan_t *plan, void *stream)
 {
     clear_error();
@@ -582,6 +637,9 @@ extern "C" int sincos_ragged_plan_launch(const sincos_ragged_plan_t *plan, void 
         return set_error(SINCOS_EINVAL, "plan_launch: null plan");
     if (plan->count == 0)
         return SINCOS_OK;
+    int rc = check_plan_device(plan, "plan_launch");
+    if (rc != SINCOS_OK)
+        return rc;
     hipError_t e = launch_ragged(plan->d_desc, plan->d_ubeg, plan->count, plan->total_units,
                                  plan->arith, plan->method, plan->shape, (hipStream_t)stream);
     return e == hipSuccess ? SINCOS_OK : hip_error(e, "plan_launch: kernel launch");
@@ -594,6 +652,9 @@ extern "C" int sincos_ragged_plan_graph_launch(sincos_ragged_plan_t *plan, void 
         return set_error(SINCOS_EINVAL, "plan_graph_launch: null plan");
     if (plan->count == 0)
         return SINCOS_OK;
+    int rc = check_plan_device(plan, "plan_graph_launch");
+    if (rc != SINCOS_OK)
+        return rc;
     hipError_t e;
     if (!plan->exec) {
         if (!plan->capture_stream &&
@@ -712,8 +773,12 @@ extern "C" int sinusoid_f32_forward(const float *t, int64_t N, const float *A, c
         return SINCOS_OK;
     if (!t || !y)
         return set_error(SINCOS_EINVAL, "sinusoid_f32_forward: null t or y with N > 0");
-    if (ranges_overlap(t, N, y, N) && t != y)
-        return set_error(SINCOS_EOVERLAP, "sinusoid_f32_forward: t partially overlaps y");
+    if (!all_aligned4({t, y, A, w, phi}))
+        return set_error(SINCOS_EINVAL, "sinusoid_f32_forward: pointers must be 4-byte aligned");
+    if ((rc = check_disjoint({{y, N, "y"}},
+                             {{t, N, "t"}, {A, K, "A"}, {w, K, "w"}, {phi, K, "phi"}},
+                             "sinusoid_f32_forward", y, t)) != SINCOS_OK)
+        return rc;
     const DeviceInfo *dev;
     if ((rc = current_device(&dev)) != SINCOS_OK)
         return rc;
@@ -744,16 +809,19 @@ extern "C" int sinusoid_f32_residual(const float *t, const float *y_obs, int64_t
     if (N > 0) {
         if (!t || !y_obs || !r)
             return set_error(SINCOS_EINVAL, "sinusoid_f32_residual: null t, y_obs or r with N > 0");
-        if (!aligned4(t) || !aligned4(y_obs) || !aligned4(r) || !aligned4(loss))
+        if (!all_aligned4({t, y_obs, r, loss, A, w, phi, workspace}))
             return set_error(SINCOS_EINVAL, "sinusoid_f32_residual: pointers must be 4-byte aligned");
-        if ((r != t && ranges_overlap(r, N, t, N)) || (r != y_obs && ranges_overlap(r, N, y_obs, N)))
-            return set_error(SINCOS_EOVERLAP, "sinusoid_f32_residual: r partially overlaps t or y_obs");
-        if (ranges_overlap(loss, 1, r, N))
-            return set_error(SINCOS_EOVERLAP, "sinusoid_f32_residual: loss overlaps r");
         const int64_t need = sinusoid_f32_residual_workspace_bytes(N);
         if (!workspace || workspace_bytes < need)
             return set_error(SINCOS_EINVAL, "sinusoid_f32_residual: workspace needs " +
                                                 std::to_string(need) + " bytes");
+        if ((rc = check_disjoint({{r, N, "r"}, {loss, 1, "loss"}, {workspace, need / 4, "workspace"}},
+                                 {{t, N, "t"}, {y_obs, N, "y_obs"}, {A, K, "A"}, {w, K, "w"},
+                                  {phi, K, "phi"}},
+                                 "sinusoid_f32_residual", r, t, y_obs)) != SINCOS_OK)
+            return rc;
+    } else if (!aligned4(loss)) {
+        return set_error(SINCOS_EINVAL, "sinusoid_f32_residual: loss must be 4-byte aligned");
     }
     const DeviceInfo *dev;
     if ((rc = current_device(&dev)) != SINCOS_OK)
@@ -789,10 +857,17 @@ extern "C" int sinusoid_f32_backward(const float *t, const float *g, int64_t N, 
         return set_error(SINCOS_EINVAL, "sinusoid_f32_backward: null gradient output");
     if (N > 0 && (!t || !g))
         return set_error(SINCOS_EINVAL, "sinusoid_f32_backward: null t or g with N > 0");
+    if (!all_aligned4({t, g, A, w, phi, gA, gw, gphi, workspace}))
+        return set_error(SINCOS_EINVAL, "sinusoid_f32_backward: pointers must be 4-byte aligned");
     const int64_t need = sinusoid_f32_backward_workspace_bytes(N, K);
     if (N > 0 && (!workspace || workspace_bytes < need))
         return set_error(SINCOS_EINVAL, "sinusoid_f32_backward: workspace needs " +
                                             std::to_string(need) + " bytes");
+    if ((rc = check_disjoint({{gA, K, "gA"}, {gw, K, "gw"}, {gphi, K, "gphi"},
+                              {N > 0 ? workspace : nullptr, need / 4, "workspace"}},
+                             {{t, N, "t"}, {g, N, "g"}, {A, K, "A"}, {w, K, "w"}, {phi, K, "phi"}},
+                             "sinusoid_f32_backward")) != SINCOS_OK)
+        return rc;
     const DeviceInfo *dev;
     if ((rc = current_device(&dev)) != SINCOS_OK)
         return rc;

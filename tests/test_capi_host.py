@@ -155,6 +155,42 @@ def test_sinusoid_validation_and_workspace(L):
     assert rc == _capi.EINVAL and "workspace" in _capi.last_error()
 
 
+def test_sinusoid_aliasing_and_alignment(L):
+    """The sinusoid calls reject outputs that overlap their inputs, the
+    parameters or each other, and misaligned arrays, before any HIP call."""
+    t, y, A, w, p = BASE, BASE + 65536, BASE + 2 * 65536, BASE + 3 * 65536, BASE + 4 * 65536
+    fwd = L.sinusoid_f32_forward
+    assert fwd(t, 16, A, w, p, 8, A + 4, None) == _capi.EOVERLAP           # y over A
+    assert "A" in _capi.last_error()
+    assert fwd(t, 16, A, w, p, 8, p - 8, None) == _capi.EOVERLAP           # y over phi
+    assert fwd(t, 16, A, w, p, 8, t + 4, None) == _capi.EOVERLAP           # y partly t
+    assert fwd(t + 2, 16, A, w, p, 8, y, None) == _capi.EINVAL             # misaligned t
+    assert fwd(t, 16, A, w + 1, p, 8, y, None) == _capi.EINVAL             # misaligned w
+    res = L.sinusoid_f32_residual
+    yo, r, loss, ws = BASE + 5 * 65536, BASE + 6 * 65536, BASE + 7 * 65536, BASE + 8 * 65536
+    assert res(t, yo, 16, A, w, p, 8, r, loss, A, 64, None) == _capi.EOVERLAP   # ws over A
+    assert res(t, yo, 16, A, w, p, 8, r, loss, r + 16, 64, None) == _capi.EOVERLAP  # ws over r
+    assert res(t, yo, 16, A, w, p, 8, r, w + 4, ws, 64, None) == _capi.EOVERLAP  # loss in w
+    assert res(t, yo, 16, A, w, p, 8, r, loss, ws + 2, 64, None) == _capi.EINVAL
+    bwd = L.sinusoid_f32_backward
+    gA, gw, gp = BASE + 9 * 65536, BASE + 10 * 65536, BASE + 11 * 65536
+    need = L.sinusoid_f32_backward_workspace_bytes(16, 8)
+    ok = (t, y, 16, A, w, p, 8, gA, gw, gp, ws, need, None)
+
+    def bad(**kw):
+        names = ("t", "g", "N", "A", "w", "phi", "K", "gA", "gw", "gphi", "ws", "wsb", "st")
+        args = dict(zip(names, ok))
+        args.update(kw)
+        return bwd(*[args[n] for n in names])
+    assert bad(gA=A) == _capi.EOVERLAP                 # in-place gradient into A
+    assert bad(gw=gA + 4) == _capi.EOVERLAP            # gw overlaps gA
+    assert bad(gphi=t + 8) == _capi.EOVERLAP           # gphi inside t
+    assert bad(ws=gp) == _capi.EOVERLAP                # workspace over gphi
+    assert bad(ws=y) == _capi.EOVERLAP                 # workspace over g
+    assert bad(gA=gA + 2) == _capi.EINVAL              # misaligned
+    assert bad(g=y + 1) == _capi.EINVAL
+
+
 def test_sinusoid_residual_validation(L):
     f = L.sinusoid_f32_residual
     wb = L.sinusoid_f32_residual_workspace_bytes
