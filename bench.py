@@ -72,12 +72,22 @@ def counter_traffic(n: int):
     return d.get("hbm_bytes_per_launch")
 
 
-def time_launches(torch, fn, steps: int, warmup: int):
-    """Run fn() warmup times, then time `steps` launches with HIP events on
-    torch's current stream (the stream the library launches on) and with the
-    host clock.  Returns (event_ms_per_launch, wall_ms_per_launch)."""
-    for _ in range(warmup):
+def time_launches(torch, fn, steps: int, warmup: int, warm_ms: float = 0.0):
+    """Run fn() warmup times (and on until warm_ms of wall time has passed),
+    then time `steps` launches with HIP events on torch's current stream (the
+    stream the library launches on) and with the host clock.  Returns
+    (event_ms_per_launch, wall_ms_per_launch).
+
+    warm_ms is for the ALU-bound kernels: after a memory-bound phase the
+    shader clock takes some milliseconds of compute to come back up, and a
+    short warmup would time part of that ramp instead of the steady state."""
+    t_warm = time.perf_counter()
+    done = 0
+    while done < warmup or (time.perf_counter() - t_warm) * 1e3 < warm_ms:
         fn()
+        done += 1
+        if done >= warmup and warm_ms > 0 and done % 8 == 0:
+            torch.cuda.synchronize()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     start = torch.cuda.Event(enable_timing=True)
@@ -137,6 +147,7 @@ def cpu_baseline(x_host, arith: int):
 # FP32 vector peak 157.3 TFLOP/s counts an FMA as 2 flops: 78.6 T VALU lane-ops
 # per second (256 CUs x 128 lanes x 2.4 GHz), each VALU instruction one op.
 VALU_PEAK_TOPS = 157.3 / 2
+ALU_WARM_MS = 30.0      # compute before timing an ALU-bound kernel (clock ramp)
 # VALU instructions per (sample, frequency) pair in the kernels' inner loops,
 # counted in the gfx950 assembly: 89 per 4 pairs (forward), 233 per 8 (adjoint).
 SINUSOID_FWD_OPS = 89 / 4
@@ -233,7 +244,8 @@ def valu_ceiling(torch):
     n, steps = 1 << 21, 256
     x = torch.rand(n, device="cuda")
     out = torch.empty_like(x)
-    ms, _ = time_launches(torch, lambda: _capi.sincos_pair_ceiling_f32(x, out, n, steps), 5, 2)
+    ms, _ = time_launches(torch, lambda: _capi.sincos_pair_ceiling_f32(x, out, n, steps), 5, 2,
+                          ALU_WARM_MS)
     tops = n * steps * 8 * PAIR_CEILING_OPS / (ms * 1e-3) / 1e12
     log("VALU ceiling (pair mix, no memory): %.3f ms, %.1f T lane-ops/s" % (ms, tops))
     return tops
@@ -254,14 +266,16 @@ def bench_sinusoid(torch, reps):
     t, A, w, phi, yobs = d(p.t), d(p.A), d(p.w), d(p.phi), d(p.y_obs)
     N, K = t.numel(), A.numel()
     y = torch.empty_like(t)
-    f_ms, _ = time_launches(torch, lambda: _capi.sinusoid_f32_forward(t, A, w, phi, y), reps, 2)
+    f_ms, _ = time_launches(torch, lambda: _capi.sinusoid_f32_forward(t, A, w, phi, y), reps, 2,
+                            ALU_WARM_MS)
     r = y - yobs
     gA, gw, gp = torch.empty_like(A), torch.empty_like(A), torch.empty_like(A)
     nb = _capi.sinusoid_f32_backward_workspace_bytes(N, K)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     a_ms, _ = time_launches(torch, lambda: _capi.sinusoid_f32_backward(
-        t, r, A, w, phi, gA, gw, gp, ws, nb), reps, 2)
-    tot_ms, _ = time_launches(torch, lambda: sinusoid_loss_and_grads(t, yobs, A, w, phi), reps, 2)
+        t, r, A, w, phi, gA, gw, gp, ws, nb), reps, 2, ALU_WARM_MS)
+    tot_ms, _ = time_launches(torch, lambda: sinusoid_loss_and_grads(t, yobs, A, w, phi), reps, 2,
+                              ALU_WARM_MS)
     ceil = valu_ceiling(torch)
     # the same fit step captured as a HIP graph (no host work per step)
     side = torch.cuda.Stream()
@@ -273,7 +287,7 @@ def bench_sinusoid(torch, reps):
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph, stream=side):
         sinusoid_loss_and_grads(t, yobs, A, w, phi)
-    graph_ms, _ = time_launches(torch, graph.replay, reps, 2)
+    graph_ms, _ = time_launches(torch, graph.replay, reps, 2, ALU_WARM_MS)
     del graph
     # composed baseline: theta matrix in torch, the plain kernel over it, then
     # rocBLAS products for the model and its gradients
@@ -287,7 +301,7 @@ def bench_sinusoid(torch, reps):
         yy = A @ S
         rr = yy - yobs
         return 0.5 * torch.dot(rr, rr), S @ rr, A * (C @ (rr * t)), A * (C @ rr)
-    c_ms, _ = time_launches(torch, composed, reps, 2)
+    c_ms, _ = time_launches(torch, composed, reps, 2, ALU_WARM_MS)
     pairs = N * K
     ops = pairs * (SINUSOID_FWD_OPS + SINUSOID_ADJ_OPS)
     del theta, S, C
@@ -335,7 +349,8 @@ def bench_huygens(torch, reps):
     P, S = xo.numel(), p.src.shape[0]
     re = torch.empty_like(xo)
     im = torch.empty_like(xo)
-    ms, _ = time_launches(torch, lambda: _capi.huygens_f32(xo, yo, src, p.k, p.L, re, im), reps, 1)
+    ms, _ = time_launches(torch, lambda: _capi.huygens_f32(xo, yo, src, p.k, p.L, re, im), reps, 1,
+                          ALU_WARM_MS)
     ceil = valu_ceiling(torch)
     sx, sy, sa, sp = (src.view(S, 4)[:, i] for i in range(4))
     chunk = 1 << 16
@@ -542,9 +557,9 @@ def main(argv=None):
         elif f == "adjoint":
             out["forms"]["adjoint"] = bench_adjoint(torch, max(5, args.steps // 4), achieved)
         elif f == "sinusoid":
-            out["forms"]["sinusoid"] = bench_sinusoid(torch, max(5, args.steps // 4))
+            out["forms"]["sinusoid"] = bench_sinusoid(torch, max(20, args.steps))
         elif f == "huygens":
-            out["forms"]["huygens"] = bench_huygens(torch, max(5, args.steps // 10))
+            out["forms"]["huygens"] = bench_huygens(torch, max(10, args.steps // 5))
         elif f == "serve":
             out["forms"]["serve"] = bench_serve(torch, value)
         torch.cuda.empty_cache()
