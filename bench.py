@@ -420,7 +420,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=40)   # 20 ms: clocks settle
     ap.add_argument("--n", type=int, default=1 << 28)
     ap.add_argument("--arith", choices=["fused", "split"], default="fused")
     ap.add_argument("--block", type=int, default=0)
