@@ -309,6 +309,10 @@ def test_sinusoid_forward_bit_exact_and_adjoint_bound(torch_dev, N, K):
     torch.cuda.synchronize()
     yo = oracle.sinusoid_forward(t, A, w, phi, threads=oracle.default_threads())
     assert_bit_exact(y.cpu().numpy(), yo, "sinusoid forward N=%d K=%d" % (N, K))
+    t2 = d(t)                              # in place: y over t
+    _capi.sinusoid_f32_forward(t2, Ad, wd, pd, t2)
+    torch.cuda.synchronize()
+    assert_bit_exact(t2.cpu().numpy(), yo, "sinusoid forward in place N=%d K=%d" % (N, K))
     g = np.random.default_rng(1).standard_normal(N).astype(np.float32)
     gA, gw, gp = (torch.empty_like(Ad) for _ in range(3))
     nb = _capi.sinusoid_f32_backward_workspace_bytes(N, K)
@@ -352,6 +356,11 @@ def test_sinusoid_residual_and_loss(torch_dev, N, K):
     _capi.sinusoid_f32_residual(td, yd2, Ad, wd, pd, yd2, loss, ws, nb, N, K)
     torch.cuda.synchronize()
     assert_bit_exact(yd2.cpu().numpy(), r_or, "residual in place N=%d" % N)
+    # in place: r over t
+    td2 = d(t)
+    _capi.sinusoid_f32_residual(td2, yd, Ad, wd, pd, td2, loss, ws, nb, N, K)
+    torch.cuda.synchronize()
+    assert_bit_exact(td2.cpu().numpy(), r_or, "residual in place over t N=%d" % N)
 
 
 def test_sinusoid_residual_empty(torch_dev):
