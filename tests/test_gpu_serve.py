@@ -118,3 +118,49 @@ def test_tight_budget_forces_waiting_and_keeps_results(torch_dev):
             assert torch.equal(device_view(torch, c.s, n).view(torch.int32), s_alone.view(torch.int32))
             assert torch.equal(device_view(torch, c.c, n).view(torch.int32), c_alone.view(torch.int32))
             srv.release(rid)
+
+
+@pytest.mark.slow
+def test_served_workload_full_sampled(torch_dev):
+    """The served workload at full size: 10,000 requests of log-uniform size
+    in [1e3, 1e7] (about 1.1e10 elements), the 8 GiB budget and four batches
+    in flight, all submitted at once.  Every request completes; each result,
+    read before its release, agrees bit for bit with the oracle on sampled
+    elements (the first 8, the last 8 and 48 random positions)."""
+    torch = torch_dev
+    from paper_cs_0406049_amd import _capi, serve, workloads
+    rs = workloads.request_stream()
+    pool = torch.from_numpy(rs.pool).cuda()
+    assert int((rs.offsets + rs.sizes).max()) <= pool.numel()
+    base = pool.data_ptr()
+    rng = np.random.default_rng(9)
+    xs, ss, cs = [], [], []
+    with serve.Server(max_inflight=4) as srv:
+        for j, (o, n) in enumerate(zip(rs.offsets, rs.sizes)):
+            srv.submit(base + 4 * int(o), int(n), tag=j)
+        left = rs.sizes.size
+        while left:
+            got = srv.poll(256, 5.0)
+            assert got, "no completion within 5 s"
+            for c in got:
+                assert c.status == _capi.OK
+                j = int(c.tag)
+                n, o = int(rs.sizes[j]), int(rs.offsets[j])
+                assert c.n == n
+                idx = np.unique(np.concatenate([np.arange(8), np.arange(n - 8, n),
+                                                rng.integers(0, n, 48)]))
+                ti = torch.from_numpy(idx).cuda()
+                ss.append(device_view(torch, c.s, n).index_select(0, ti).cpu().numpy())
+                cs.append(device_view(torch, c.c, n).index_select(0, ti).cpu().numpy())
+                xs.append(rs.pool[o + idx])
+                srv.release(c.id)
+            left -= len(got)
+        st = srv.stats()
+    assert st["completed"] == rs.sizes.size and st["failed"] == 0
+    assert st["budget_in_use"] == 0 and st["budget_peak"] <= 8 << 30
+    x = np.concatenate(xs)
+    so, co = oracle.sincos(x, 0, 0, threads=oracle.default_threads())
+    assert_bit_exact(np.concatenate(ss), so, "served full workload sin", x)
+    assert_bit_exact(np.concatenate(cs), co, "served full workload cos", x)
+    log("served full workload: %d requests, %d batches, inflight peak %d, %d sampled outputs" % (
+        st["completed"], st["batches"], st["inflight_peak"], x.size))
