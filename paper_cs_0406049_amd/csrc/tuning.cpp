@@ -7,8 +7,8 @@
 //    "ragged": {"block": 512, "unroll": 2, "grid": 0}}
 // Both forms and all three fields are optional; a missing field takes the
 // built-in default (kBuiltinShape).  Anything else (unknown keys,
-// non-integers, trailing text) is rejected, leaving the current shapes
-// unchanged.
+// non-integers, numbers JSON does not allow, escapes in keys, trailing text)
+// is rejected, leaving the current shapes unchanged.
 #include "../../include/sincos.h"
 #include "internal.hpp"
 
@@ -49,9 +49,9 @@ struct Reader {
     const char *p;
     std::string err;
 
-    void ws()
+    void ws()  // JSON whitespace only
     {
-        while (*p && std::isspace((unsigned char)*p))
+        while (*p == ' ' || *p == '\t' || *p == '\n' || *p == '\r')
             ++p;
     }
     bool fail(const std::string &m)
@@ -95,6 +95,8 @@ struct Reader {
         }
         if (!std::isdigit((unsigned char)*p))
             return fail("expected an integer");
+        if (p[0] == '0' && std::isdigit((unsigned char)p[1]))
+            return fail("leading zero");
         long long v = 0;
         while (std::isdigit((unsigned char)*p)) {
             v = v * 10 + (*p++ - '0');
