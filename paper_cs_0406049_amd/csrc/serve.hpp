@@ -2,6 +2,7 @@
 // the first-fit arena allocator for output buffers.
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 #include <map>
 
