@@ -22,6 +22,14 @@ COMPLETION_DTYPE = np.dtype([("id", np.int64), ("tag", np.uint64), ("status", np
 assert COMPLETION_DTYPE.itemsize == ctypes.sizeof(_capi.Completion)
 
 
+class _DeviceArray:
+    """A device address as a float32 array (CUDA array interface)."""
+
+    def __init__(self, ptr, n):
+        self.__cuda_array_interface__ = {"shape": (int(n),), "typestr": "<f4",
+                                         "data": (int(ptr), False), "version": 2}
+
+
 class Server:
     def __init__(self, budget_bytes: int = 8 << 30, max_inflight: int = 4,
                  max_batch_requests: int = 4096, max_batch_elems: int = 0,
@@ -54,6 +62,18 @@ class Server:
 
     def release(self, rid: int) -> None:
         _capi._check(_capi.lib().sincos_server_release(self._h, int(rid)))
+
+    @staticmethod
+    def outputs(comp):
+        """A completed request's (s, c) as float32 tensors that alias the
+        server's output buffers (no copy).  They stay valid until the request
+        is released; clone them to keep the values."""
+        import torch
+        if comp.status != _capi.OK or not comp.s or not comp.c:
+            raise ValueError("the completion carries no outputs (failed, cancelled or "
+                             "auto-released)")
+        return (torch.as_tensor(_DeviceArray(comp.s, comp.n), device="cuda"),
+                torch.as_tensor(_DeviceArray(comp.c, comp.n), device="cuda"))
 
     def stats(self) -> dict:
         st = _capi.ServerStats()

@@ -36,3 +36,16 @@ def test_readme_python_example():
     g = ns["theta"].grad.cpu().numpy()
     want = (co.astype(np.float32) - so.astype(np.float32)).astype(np.float32)
     assert np.array_equal(g.view(np.uint32), want.view(np.uint32))
+    # the fit step: the loss of the oracle's forward model, the same gradients as autograd
+    from paper_cs_0406049_amd.autograd import sinusoid
+    th, Ah, wh, ph = (ns[k].cpu().numpy() for k in ("t", "A", "w", "phi"))
+    y_obs = ns["torch"].sin(3 * ns["t"])
+    r = oracle.sinusoid_forward(th, Ah, wh, ph).astype(np.float64) - y_obs.cpu().numpy()
+    assert abs(float(ns["loss"]) - 0.5 * float((r * r).sum())) <= 1e-5 * 0.5 * float((r * r).sum())
+    Ap, wp, pp = (ns[k].clone().requires_grad_(True) for k in ("A", "w", "phi"))
+    (0.5 * ((sinusoid(ns["t"], Ap, wp, pp) - y_obs) ** 2).sum()).backward()
+    for got, ref in ((ns["gA"], Ap.grad), (ns["gw"], wp.grad), (ns["gphi"], pp.grad)):
+        assert torch.equal(got, ref)
+    # the served request: the same bits as the plain call
+    assert_bit_exact(ns["s_req"].cpu().numpy(), so, "README served sin", xh)
+    assert_bit_exact(ns["c_req"].cpu().numpy(), co, "README served cos", xh)
