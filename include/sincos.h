@@ -348,8 +348,9 @@ SINCOS_API int sincos_server_destroy(sincos_server_t *srv);
  *       limits of sincos_launch_t.  Forms and fields left out get the
  *       built-in defaults (plain 64, 1, 0; ragged 256, 1, 0), so NULL or
  *       "{}" restores them.
- * Errors: EINVAL for text outside that form (unknown keys, non-integers,
- * trailing text) or values out of range; the current shapes are then kept.
+ * Errors: EINVAL for text outside that form (unknown or repeated keys,
+ * non-integers, whitespace or numbers JSON does not allow, trailing text)
+ * or values out of range; the current shapes are then kept.
  * Thread-safe.  Takes effect for calls that start after it returns; plans
  * keep the shape they were created with.  No GPU is needed.              */
 SINCOS_API int sincos_set_tuning(const char *json);

@@ -7,8 +7,8 @@
 //    "ragged": {"block": 512, "unroll": 2, "grid": 0}}
 // Both forms and all three fields are optional; a missing field takes the
 // built-in default (kBuiltinShape).  Anything else (unknown keys,
-// non-integers, numbers JSON does not allow, escapes in keys, trailing text)
-// is rejected, leaving the current shapes unchanged.
+// non-integers, numbers JSON does not allow, escapes in keys, a repeated key,
+// trailing text) is rejected, leaving the current shapes unchanged.
 #include "../../include/sincos.h"
 #include "internal.hpp"
 
@@ -118,19 +118,19 @@ struct Reader {
             ++p;
             return true;
         }
+        bool seen[3] = {false, false, false};
         for (;;) {
             std::string k;
             int v = 0;
             if (!key(k) || !expect(':') || !integer(v))
                 return false;
-            if (k == "block")
-                sh.block = v;
-            else if (k == "unroll")
-                sh.unroll = v;
-            else if (k == "grid")
-                sh.grid = v;
-            else
+            const int f = k == "block" ? 0 : k == "unroll" ? 1 : k == "grid" ? 2 : -1;
+            if (f < 0)
                 return fail("unknown field \"" + k + "\"");
+            if (seen[f])
+                return fail("repeated field \"" + k + "\"");
+            seen[f] = true;
+            (f == 0 ? sh.block : f == 1 ? sh.unroll : sh.grid) = v;
             ws();
             if (*p == ',') {
                 ++p;
@@ -147,19 +147,19 @@ struct Reader {
         if (*p == '}') {
             ++p;
         } else {
+            bool seen[2] = {false, false};
             for (;;) {
                 std::string k;
                 if (!key(k) || !expect(':'))
                     return false;
-                if (k == "plain") {
-                    if (!shape(out[kFormPlain]))
-                        return false;
-                } else if (k == "ragged") {
-                    if (!shape(out[kFormRagged]))
-                        return false;
-                } else {
+                const int form = k == "plain" ? kFormPlain : k == "ragged" ? kFormRagged : -1;
+                if (form < 0)
                     return fail("unknown form \"" + k + "\" (plain or ragged)");
-                }
+                if (seen[form])
+                    return fail("repeated form \"" + k + "\"");
+                seen[form] = true;
+                if (!shape(out[form]))
+                    return false;
                 ws();
                 if (*p == ',') {
                     ++p;

@@ -139,6 +139,8 @@ def test_tuning_accepts_exactly_the_valid_documents(L, doc, indent):
 @example(text='{"ragged": {}}\x0b')
 @example(text='{"plain": {"grid": -0}}')
 @example(text='{"plain": {"block": 1e2}}')
+@example(text='{"ragged": {"block": 128}, "ragged": {"grid": 1}}')
+@example(text='{"plain": {"block": 128, "block": 64}}')
 @given(text=st.text(alphabet='{}[]:,"-. 0123456789eE\t\x0b\x0cplainraggedblockunrollgridx\\',
                     max_size=80))
 def test_tuning_parser_never_accepts_what_json_rejects(L, text):
