@@ -127,9 +127,11 @@ SINCOS_API int sincos_f32_interleaved(const float *x, float *out, int64_t n, int
  * Both tables are host memory, read before the call returns.  Each segment
  * obeys the plain form's aliasing rules; in addition no output may overlap
  * any other segment's input or output (inputs may be shared).
- * The descriptor table is staged through library-owned pinned and device
- * buffers (a small ring guarded by events), so the call must not be made
- * while `stream` is being captured into a graph: use a plan for that.     */
+ * Up to 64 non-empty segments the descriptor table is passed in the kernel
+ * arguments; larger tables are staged through library-owned pinned and
+ * device buffers (a small ring guarded by events).  Either way the call
+ * must not be made while `stream` is being captured into a graph: use a
+ * plan for that.                                                          */
 typedef struct {
     const float *x;
     float *s;

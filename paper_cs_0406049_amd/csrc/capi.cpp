@@ -334,6 +334,23 @@ int stage_and_launch(const RaggedTable &t, char *host, char *dev_buf, int arith,
     return SINCOS_OK;
 }
 
+int launch_table_inline(const RaggedTable &t, int arith, int method, const LaunchShape &shape,
+                        const DeviceInfo &dev, hipStream_t stream)
+{
+    const int32_t count = (int32_t)t.desc.size();
+    if (count == 0)
+        return SINCOS_OK;
+    if (count > kInlineSegs)
+        return set_error(SINCOS_EINVAL, "ragged: table too large to pass inline");
+    const int64_t total = t.ubeg.back();
+    RaggedInline tab{};
+    std::memcpy(tab.desc, t.desc.data(), sizeof(RaggedDesc) * (size_t)count);
+    std::memcpy(tab.ubeg, t.ubeg.data(), sizeof(int64_t) * (size_t)(count + 1));
+    const hipError_t e = launch_ragged_inline(tab, count, total, arith, method,
+                                              resolve_ragged_shape(shape, total, dev), stream);
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "ragged: kernel launch");
+}
+
 int grow_staging(StagingBuffers &b, size_t bytes)
 {
     if (b.cap >= bytes)
@@ -372,6 +389,8 @@ int ragged_enqueue(const RaggedTable &t, int arith, int method, const LaunchShap
 {
     if (t.desc.empty())
         return SINCOS_OK;
+    if (t.desc.size() <= (size_t)kInlineSegs)  // small tables need no staging
+        return launch_table_inline(t, arith, method, shape, dev, stream);
     StageRing &ring = ring_for(dev.device);
     std::lock_guard<std::mutex> lk(ring.mu);
     StageSlot &slot = ring.slots[ring.next];

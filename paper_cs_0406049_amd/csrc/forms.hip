@@ -5,6 +5,7 @@
 #include "stream.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace mi355 {
 
@@ -84,10 +85,13 @@ __global__ void __launch_bounds__(64) k_interleaved_tail(const float *x, float *
 // its first segment by binary search and then walks forward, so segment
 // lookups cost O(1) per unit.  Segment fields are wave-uniform (scalar loads).
 
-template <Arith A, Method M, int U>
-__global__ void __launch_bounds__(1024) k_ragged(const RaggedDesc *__restrict__ desc,
-                                                 const int64_t *__restrict__ ubeg, int32_t count,
-                                                 int64_t total_units, int64_t per_block)
+// The per-workgroup body over a table of descriptors and unit offsets.  Tab
+// is either a pair of device pointers (staged or planned tables) or the
+// table itself passed as a kernel argument (small batches): both index as
+// tab.desc[j] and tab.ubeg[j].
+template <Arith A, Method M, int U, class Tab>
+__device__ __forceinline__ void ragged_block(const Tab &tab, int32_t count, int64_t total_units,
+                                             int64_t per_block)
 {
     const int64_t u0 = (int64_t)blockIdx.x * per_block;
     const int64_t u1 = min(u0 + per_block, total_units);
@@ -96,7 +100,7 @@ __global__ void __launch_bounds__(1024) k_ragged(const RaggedDesc *__restrict__ 
     int lo = 0, hi = count - 1;
     while (lo < hi) {  // largest j with ubeg[j] <= u0
         const int mid = (lo + hi + 1) >> 1;
-        if (ubeg[mid] <= u0)
+        if (tab.ubeg[mid] <= u0)
             lo = mid;
         else
             hi = mid - 1;
@@ -104,10 +108,10 @@ __global__ void __launch_bounds__(1024) k_ragged(const RaggedDesc *__restrict__ 
     int seg = lo;
     const int64_t bd = blockDim.x;
     for (int64_t unit = u0; unit < u1; ++unit) {
-        while (ubeg[seg + 1] <= unit)
+        while (tab.ubeg[seg + 1] <= unit)
             ++seg;
-        const RaggedDesc d = desc[seg];
-        const int64_t local = unit - ubeg[seg];
+        const RaggedDesc d = tab.desc[seg];
+        const int64_t local = unit - tab.ubeg[seg];
         if (d.vec) {
             if (local == 0) {
                 const int t = threadIdx.x;
@@ -128,6 +132,28 @@ __global__ void __launch_bounds__(1024) k_ragged(const RaggedDesc *__restrict__ 
             stream_scalar_tile<A, M, U>(d.x, d.s, d.c, local * bd * U * 4 + threadIdx.x, d.n, bd);
         }
     }
+}
+
+struct RaggedPtrs {
+    const RaggedDesc *__restrict__ desc;
+    const int64_t *__restrict__ ubeg;
+};
+
+template <Arith A, Method M, int U>
+__global__ void __launch_bounds__(1024) k_ragged(const RaggedDesc *__restrict__ desc,
+                                                 const int64_t *__restrict__ ubeg, int32_t count,
+                                                 int64_t total_units, int64_t per_block)
+{
+    ragged_block<A, M, U>(RaggedPtrs{desc, ubeg}, count, total_units, per_block);
+}
+
+// Small tables travel in the kernel arguments: no staging copy before the
+// launch (the runtime copies the arguments when it enqueues the kernel).
+template <Arith A, Method M, int U>
+__global__ void __launch_bounds__(1024) k_ragged_inline(const RaggedInline tab, int32_t count,
+                                                        int64_t total_units, int64_t per_block)
+{
+    ragged_block<A, M, U>(tab, count, total_units, per_block);
 }
 
 // ---------------------------------------------------------------------------
@@ -479,15 +505,22 @@ __global__ void __launch_bounds__(256) k_pair_ceiling(const float *x, float *out
 
 namespace {
 
-template <Arith A, Method M>
-hipError_t launch_ragged_am(const RaggedDesc *desc, const int64_t *ubeg, int32_t count,
-                            int64_t total_units, const LaunchShape &sh, hipStream_t st)
+// Tab: RaggedPtrs (device table) or RaggedInline (table in the arguments).
+template <Arith A, Method M, class Tab>
+hipError_t launch_ragged_am(const Tab &tab, int32_t count, int64_t total_units,
+                            const LaunchShape &sh, hipStream_t st)
 {
     const int64_t grid = std::max(1, sh.grid);
     const int64_t per = (total_units + grid - 1) / grid;
-#define MI355_RAGGED(UU)                                                                     \
-    hipLaunchKernelGGL((k_ragged<A, M, UU>), dim3((unsigned)grid), dim3(sh.block), 0, st, desc, \
-                       ubeg, count, total_units, per)
+#define MI355_RAGGED(UU)                                                                          \
+    do {                                                                                          \
+        if constexpr (std::is_same<Tab, RaggedInline>::value)                                     \
+            hipLaunchKernelGGL((k_ragged_inline<A, M, UU>), dim3((unsigned)grid), dim3(sh.block),  \
+                               0, st, tab, count, total_units, per);                              \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_ragged<A, M, UU>), dim3((unsigned)grid), dim3(sh.block), 0, st, \
+                               tab.desc, tab.ubeg, count, total_units, per);                      \
+    } while (0)
     switch (sh.unroll) {
     case 1: MI355_RAGGED(1); break;
     case 2: MI355_RAGGED(2); break;
@@ -496,6 +529,24 @@ hipError_t launch_ragged_am(const RaggedDesc *desc, const int64_t *ubeg, int32_t
     }
 #undef MI355_RAGGED
     return hipGetLastError();
+}
+
+template <class Tab>
+hipError_t launch_ragged_tab(const Tab &tab, int32_t count, int64_t total_units, int arith,
+                             int method, const LaunchShape &sh, hipStream_t st)
+{
+    const bool m2 = method == (int)Method::Arctan;
+    switch (arith) {
+    case (int)Arith::Split:
+        return m2 ? launch_ragged_am<Arith::Split, Method::Arctan>(tab, count, total_units, sh, st)
+                  : launch_ragged_am<Arith::Split, Method::Normalized>(tab, count, total_units, sh, st);
+    case (int)Arith::Contract:
+        return m2 ? launch_ragged_am<Arith::Contract, Method::Arctan>(tab, count, total_units, sh, st)
+                  : launch_ragged_am<Arith::Contract, Method::Normalized>(tab, count, total_units, sh, st);
+    default:
+        return m2 ? launch_ragged_am<Arith::Fused, Method::Arctan>(tab, count, total_units, sh, st)
+                  : launch_ragged_am<Arith::Fused, Method::Normalized>(tab, count, total_units, sh, st);
+    }
 }
 
 }  // namespace
@@ -529,18 +580,15 @@ hipError_t launch_ragged(const RaggedDesc *desc, const int64_t *ubeg, int32_t co
                          int64_t total_units, int arith, int method, const LaunchShape &sh,
                          hipStream_t st)
 {
-    const bool m2 = method == (int)Method::Arctan;
-    switch (arith) {
-    case (int)Arith::Split:
-        return m2 ? launch_ragged_am<Arith::Split, Method::Arctan>(desc, ubeg, count, total_units, sh, st)
-                  : launch_ragged_am<Arith::Split, Method::Normalized>(desc, ubeg, count, total_units, sh, st);
-    case (int)Arith::Contract:
-        return m2 ? launch_ragged_am<Arith::Contract, Method::Arctan>(desc, ubeg, count, total_units, sh, st)
-                  : launch_ragged_am<Arith::Contract, Method::Normalized>(desc, ubeg, count, total_units, sh, st);
-    default:
-        return m2 ? launch_ragged_am<Arith::Fused, Method::Arctan>(desc, ubeg, count, total_units, sh, st)
-                  : launch_ragged_am<Arith::Fused, Method::Normalized>(desc, ubeg, count, total_units, sh, st);
-    }
+    return launch_ragged_tab(RaggedPtrs{desc, ubeg}, count, total_units, arith, method, sh, st);
+}
+
+hipError_t launch_ragged_inline(const RaggedInline &tab, int32_t count, int64_t total_units,
+                                int arith, int method, const LaunchShape &sh, hipStream_t st)
+{
+    if (count < 1 || count > kInlineSegs)
+        return hipErrorInvalidValue;
+    return launch_ragged_tab(tab, count, total_units, arith, method, sh, st);
 }
 
 int64_t ragged_units(const RaggedDesc &d, const LaunchShape &sh)

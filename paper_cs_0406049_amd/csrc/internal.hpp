@@ -63,6 +63,18 @@ hipError_t launch_pair_ceiling(const float *x, float *out, int64_t n, int32_t re
 hipError_t launch_ragged(const RaggedDesc *desc, const int64_t *ubeg, int32_t count,
                          int64_t total_units, int arith, int method, const LaunchShape &shape,
                          hipStream_t stream);
+
+// A small ragged table passed whole as a kernel argument (3.6 KB), so the
+// launch needs no staging copy: up to kInlineSegs non-empty segments.
+constexpr int kInlineSegs = 64;
+struct RaggedInline {
+    RaggedDesc desc[kInlineSegs];
+    int64_t ubeg[kInlineSegs + 1];
+};
+static_assert(sizeof(RaggedInline) <= 3600, "kernel arguments stay well under 4 KB");
+hipError_t launch_ragged_inline(const RaggedInline &tab, int32_t count, int64_t total_units,
+                                int arith, int method, const LaunchShape &shape,
+                                hipStream_t stream);
 hipError_t launch_backward(const float *s, const float *c, const float *gs, const float *gc,
                            float *gx, int64_t n, hipStream_t stream);
 hipError_t launch_sinusoid_forward(const float *t, int64_t N, const float *A, const float *w,
@@ -115,8 +127,12 @@ void free_staging(StagingBuffers &b);
 // passed the launch.
 int stage_and_launch(const RaggedTable &t, char *host, char *dev_buf, int arith, int method,
                      const LaunchShape &shape, const DeviceInfo &dev, hipStream_t stream);
-// Stage the table through the library's pinned/device ring and launch the
-// ragged kernel on `stream`.  Returns a sincos status.
+// Launch a table of at most kInlineSegs segments with the table in the
+// kernel arguments (nothing to stage or keep alive).
+int launch_table_inline(const RaggedTable &t, int arith, int method, const LaunchShape &shape,
+                        const DeviceInfo &dev, hipStream_t stream);
+// Launch the ragged kernel on `stream`: small tables inline, larger ones
+// staged through the library's pinned/device ring.  Returns a sincos status.
 int ragged_enqueue(const RaggedTable &t, int arith, int method, const LaunchShape &shape,
                    const DeviceInfo &dev, hipStream_t stream);
 

@@ -131,11 +131,15 @@ public:
             table_.elements = 0;
             for (Request *r : batch)
                 table_add(table_, r->x, r->s, r->c, r->n, shape);
-            rc = grow_staging(sl.staging, staged_bytes(table_));
-            if (rc != SINCOS_OK)
-                return rc;
-            rc = stage_and_launch(table_, sl.staging.host, sl.staging.dev, arith_, method_, shape,
-                                  *dev_, sl.stream);
+            if (table_.desc.size() <= (size_t)kInlineSegs) {
+                // small batch: the table travels in the kernel arguments
+                rc = launch_table_inline(table_, arith_, method_, shape, *dev_, sl.stream);
+            } else {
+                rc = grow_staging(sl.staging, staged_bytes(table_));
+                if (rc == SINCOS_OK)
+                    rc = stage_and_launch(table_, sl.staging.host, sl.staging.dev, arith_,
+                                          method_, shape, *dev_, sl.stream);
+            }
             if (rc != SINCOS_OK)
                 return rc;
         }

@@ -55,6 +55,29 @@ def test_ragged_mixed_lengths(torch_dev, launch):
     _check_segments(xs_h, segs, "ragged %r" % (launch,))
 
 
+@pytest.mark.parametrize("nonempty,empty", [(1, 0), (63, 0), (64, 0), (64, 9), (65, 0), (200, 3)])
+@pytest.mark.parametrize("arith,method", [(0, 0), (1, 1)])
+def test_ragged_inline_and_staged_tables(torch_dev, nonempty, empty, arith, method):
+    """Up to 64 non-empty segments the table travels in the kernel arguments;
+    beyond, it is staged through device memory.  Both give the oracle's
+    bits, at and around the boundary, with empty segments interleaved."""
+    torch = torch_dev
+    from paper_cs_0406049_amd import _capi
+    rng = np.random.default_rng(nonempty * 31 + empty)
+    lens = [int(v) for v in rng.integers(1, 20000, nonempty)]
+    for k in range(empty):
+        lens.insert(int(rng.integers(0, len(lens) + 1)), 0)
+    xs_h, segs = _segments(torch, lens, nonempty + empty)
+    _capi.sincos_f32_ragged(segs, lens, arith=arith, method=method)
+    torch.cuda.synchronize()
+    for j, (xh, (_, s, c)) in enumerate(zip(xs_h, segs)):
+        if xh.size == 0:
+            continue
+        so, co = oracle.sincos(xh, arith, method)
+        assert_bit_exact(s.cpu().numpy(), so, "ragged %d+%d seg %d sin" % (nonempty, empty, j), xh)
+        assert_bit_exact(c.cpu().numpy(), co, "ragged %d+%d seg %d cos" % (nonempty, empty, j), xh)
+
+
 def test_tuned_default_shapes_apply_and_keep_bits(torch_dev):
     """Shapes installed with sincos_set_tuning are used by calls that pass
     none (a ragged plan reports them) and leave every output bit unchanged."""
