@@ -78,6 +78,12 @@ def test_replay_poisson_stream(torch_dev):
         comp = srv.replay(xs, sizes, arr)
         st = srv.stats()
     assert np.all(comp["status"] == 0)
+    with serve.Server(auto_release=True) as srv:      # auto-released: no outputs to alias
+        srv.submit(xs[0], int(sizes[0]))
+        done = srv.poll(1, 5.0)
+        assert done and done[0].status == 0
+        with pytest.raises(ValueError):
+            srv.outputs(done[0])
     summ = serve.latency_summary(comp)
     log("replay: %s, batches %d, inflight peak %d" % (summ, st["batches"], st["inflight_peak"]))
     assert st["batches"] < comp.size
