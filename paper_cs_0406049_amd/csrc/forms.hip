@@ -286,14 +286,34 @@ __global__ void __launch_bounds__(kFwdBlock) k_sinusoid_fwd(const float *t, int6
     }
 }
 
+// Sum of p[start], p[start + step], ... below n, added in that order.  The
+// loads go out eight at a time so their latencies overlap; the additions
+// keep the order, so the result does not depend on the grouping.
+__device__ __forceinline__ float strided_sum(const float *p, int64_t n, int64_t start,
+                                             int64_t step)
+{
+    float acc = 0.0f;
+    int64_t j = start;
+    for (; j + 7 * step < n; j += 8 * step) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            v[u] = p[j + u * step];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            acc += v[u];
+    }
+    for (; j < n; j += step)
+        acc += p[j];
+    return acc;
+}
+
 // loss = 1/2 * (sum of the workgroup partials): one workgroup, strided
 // per-thread sums, then a fixed 256-way tree.
 __global__ void __launch_bounds__(256) k_loss_reduce(const float *part, int64_t nparts, float *loss)
 {
     __shared__ float red[256];
-    float acc = 0.0f;
-    for (int64_t j = threadIdx.x; j < nparts; j += 256)
-        acc += part[j];
+    const float acc = strided_sum(part, nparts, threadIdx.x, 256);
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
@@ -376,10 +396,7 @@ __global__ void __launch_bounds__(256) k_sinusoid_reduce(const float *partial, i
     const int j = blockIdx.y;  // 0: A, 1: phi, 2: w
     __shared__ float red[256];
     const float *row = partial + ((int64_t)j * Kpad + k) * nparts;
-    float acc = 0.f;
-    for (int64_t ch = threadIdx.x; ch < nparts; ch += blockDim.x)
-        acc += row[ch];
-    red[threadIdx.x] = acc;
+    red[threadIdx.x] = strided_sum(row, nparts, threadIdx.x, blockDim.x);
     __syncthreads();
     for (int h = blockDim.x / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h)
