@@ -83,6 +83,9 @@ def lib():
             L.oracle_pair_variant.argtypes = [ctypes.c_float, c_int, c_int, c_int, fp, fp]
             L.oracle_pair_general.argtypes = [ctypes.c_float, c_int, c_int, fp, c_int, fp, c_int,
                                               c_int, fp, fp]
+            L.oracle_pair_variant_f32.argtypes = [fp, fp, fp, i64, c_int, c_int, c_int, c_int]
+            L.oracle_pair_general_f32.argtypes = [fp, fp, fp, i64, c_int, c_int, fp, c_int, fp,
+                                                  c_int, c_int, c_int]
             L.oracle_error_scan_general.argtypes = [u32, u32, u32, c_int, c_int, fp, c_int, fp,
                                                     c_int, c_int, c_int, dp, dp, dp, fp, fp,
                                                     ctypes.POINTER(ctypes.c_int64)]
@@ -210,6 +213,35 @@ def pair_general(q1: float, ndoub: int, ss, cc, arith: int = FUSED, fix: bool = 
     lib().oracle_pair_general(ctypes.c_float(q1), arith, ndoub, _f32p(ss), ss.size, _f32p(cc),
                               cc.size, int(fix), ctypes.byref(s), ctypes.byref(c))
     return np.float32(s.value), np.float32(c.value)
+
+
+def sincos_variant(x, arith: int = FUSED, method: int = METHOD1, variant: int = VARIANT_LISTING,
+                   threads: int = 1):
+    """Pairs of the angles x with one of the Sec. II ablations (pair_variant
+    after the reduction of step 1)."""
+    x = _c32(x)
+    s = np.empty_like(x)
+    c = np.empty_like(x)
+    rc = lib().oracle_pair_variant_f32(_f32p(x), _f32p(s), _f32p(c), x.size, arith, method,
+                                       int(variant), threads)
+    if rc != 0:
+        raise ValueError("oracle_pair_variant_f32 failed")
+    return s, c
+
+
+def sincos_general(x, ndoub: int, ss, cc, arith: int = FUSED, fix: bool = True,
+                   threads: int = 1):
+    """Pairs of the angles x with the general-doubling ablation (pair_general
+    after the reduction of step 1)."""
+    x, ss, cc = _c32(x), _c32(ss), _c32(cc)
+    s = np.empty_like(x)
+    c = np.empty_like(x)
+    rc = lib().oracle_pair_general_f32(_f32p(x), _f32p(s), _f32p(c), x.size, arith, int(ndoub),
+                                       _f32p(ss), ss.size, _f32p(cc), cc.size, int(bool(fix)),
+                                       threads)
+    if rc != 0:
+        raise ValueError("oracle_pair_general_f32 failed")
+    return s, c
 
 
 def error_scan_general(bits_lo: int, bits_hi: int, ndoub: int, ss, cc, stride: int = 1,

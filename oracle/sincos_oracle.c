@@ -405,6 +405,50 @@ int oracle_pair_from_reduced_f32(const float *q, float *s, float *c, int64_t n, 
     return run_chunks(reduced_chunk, &j, n, threads);
 }
 
+/* The ablations over arrays of angles (step 1, then oracle_pair_variant or
+ * oracle_pair_general on the reduced angle), for comparison with GPU
+ * kernels that compute the same variants.                                  */
+struct ablation_job {
+    const float *x;
+    float *s, *c;
+    int arith, method, variant;       /* variant >= 0: oracle_pair_variant  */
+    int ndoub, ns, nc, fix;           /* variant < 0: oracle_pair_general   */
+    const float *ss, *cc;
+};
+
+static void ablation_chunk(void *job, int64_t lo, int64_t hi)
+{
+    struct ablation_job *j = (struct ablation_job *)job;
+    for (int64_t i = lo; i < hi; i++) {
+        const float q1 = oracle_reduce(j->x[i]);
+        if (j->variant >= 0)
+            oracle_pair_variant(q1, j->arith, j->method, j->variant, &j->s[i], &j->c[i]);
+        else
+            oracle_pair_general(q1, j->arith, j->ndoub, j->ss, j->ns, j->cc, j->nc, j->fix,
+                                &j->s[i], &j->c[i]);
+    }
+}
+
+int oracle_pair_variant_f32(const float *x, float *s, float *c, int64_t n, int arith, int method,
+                            int variant, int threads)
+{
+    if (n < 0 || (n > 0 && (!x || !s || !c)) || variant < 0 || variant > 3)
+        return -1;
+    struct ablation_job j = {x, s, c, arith, method, variant, 0, 0, 0, 0, NULL, NULL};
+    return run_chunks(ablation_chunk, &j, n, threads);
+}
+
+int oracle_pair_general_f32(const float *x, float *s, float *c, int64_t n, int arith, int ndoub,
+                            const float *ss, int ns, const float *cc, int nc, int fix,
+                            int threads)
+{
+    if (n < 0 || (n > 0 && (!x || !s || !c)) || !ss || !cc || ns < 1 || ns > 16 || nc < 1 ||
+        nc > 16 || ndoub < 0 || ndoub > 8)
+        return -1;
+    struct ablation_job j = {x, s, c, arith, 0, -1, ndoub, ns, nc, fix, ss, cc};
+    return run_chunks(ablation_chunk, &j, n, threads);
+}
+
 /* Reduction alone, elementwise.                                             */
 int oracle_reduce_f32(const float *x, float *q, int64_t n)
 {

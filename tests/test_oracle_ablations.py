@@ -165,3 +165,30 @@ def test_fewer_doublings_need_longer_series(orc):
     assert max_err(1, 4, 3) > 1e-5
     assert max_err(2, 3, 3) > 2e-6
     assert max_err(3, 3, 3) < 6e-7
+
+
+def test_array_drivers_follow_the_scalar_ablations(orc):
+    """The array drivers reduce each angle (step 1) and apply the scalar
+    ablation: the listing variant and the general form with n = 2, the
+    printed series and the fix are the method itself over whole arrays, and
+    every element of the other variants equals the scalar function."""
+    x = np.random.default_rng(4).uniform(-300, 300, 4001).astype(np.float32)
+    s0, c0 = oracle.sincos(x)
+    k = oracle.constants(oracle.METHOD1)
+    ss, cc = k[1:5], k[5:8]
+    for arith in (oracle.FUSED, oracle.SPLIT):
+        s0, c0 = oracle.sincos(x, arith)
+        s1, c1 = oracle.sincos_variant(x, arith, oracle.METHOD1, oracle.VARIANT_LISTING)
+        s2, c2 = oracle.sincos_general(x, 2, ss, cc, arith, fix=True)
+        for a, b in ((s0, s1), (c0, c1), (s0, s2), (c0, c2)):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    q = oracle.reduce(x[:300])
+    for variant in (oracle.VARIANT_NO_FIX, oracle.VARIANT_TEXT_FIX, oracle.VARIANT_EQ2):
+        s, c = oracle.sincos_variant(x[:300], oracle.SPLIT, oracle.METHOD2, variant)
+        want = [oracle.pair_variant(float(v), oracle.SPLIT, oracle.METHOD2, variant) for v in q]
+        assert [(a, b) for a, b in zip(s, c)] == want
+    from oracle.series_fit import fit_series
+    ss4, cc4 = fit_series(4, 3, 2)
+    s, c = oracle.sincos_general(x[:300], 4, ss4, cc4, oracle.FUSED, fix=False)
+    want = [oracle.pair_general(float(v), 4, ss4, cc4, oracle.FUSED, fix=False) for v in q]
+    assert [(a, b) for a, b in zip(s, c)] == want
