@@ -20,6 +20,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -209,6 +210,53 @@ def bench_variants(torch, reps, x, s, c):
         gbs = BYTES_PER_ELEM * n / (ms * 1e-3) / 1e9
         res[name] = {"kernel_ms": round(ms, 4), "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
                      "GBps": round(gbs, 1), "per_byte_vs_plain": round(base / ms, 4)}
+    return res
+
+
+ABLATION_TERMS = {0: (6, 6), 1: (5, 4), 2: (4, 3), 3: (3, 3), 4: (3, 2), 5: (2, 2)}
+
+
+def taylor_series(ndoub, ns, nc):
+    """Taylor coefficients of sin and cos of a q, a = 2 pi / 2^ndoub, in the
+    form the doublings kernel takes (s1 = q (ss0 + ss1 q^2 + ...), c1 = 1 +
+    q^2 (cc0 + cc1 q^2 + ...)).  The timing does not depend on the values."""
+    a = 2.0 * math.pi / 2.0 ** ndoub
+    ss = [(-1) ** k * a ** (2 * k + 1) / math.factorial(2 * k + 1) for k in range(ns)]
+    cc = [(-1) ** (k + 1) * a ** (2 * k + 2) / math.factorial(2 * k + 2) for k in range(nc)]
+    return ss, cc
+
+
+def bench_ablations(torch, reps, x, s, c):
+    """The Sec. II ablations over the roofline arrays, in A/B rounds against
+    the plain kernel: the method without its fix, with the text's fix, with
+    the eq. (2) doubling, and n = 0..5 doublings after series of the lengths
+    the ablation table uses.  All move 12 bytes per element."""
+    import numpy as np
+    from paper_cs_0406049_amd import _capi
+    n = x.numel()
+    cases = [("plain", lambda: _capi.sincos_f32(x, s, c, n), None)]
+    for name, v in (("no_fix", _capi.VARIANT_NO_FIX), ("text_fix", _capi.VARIANT_TEXT_FIX),
+                    ("eq2_doubling", _capi.VARIANT_EQ2)):
+        cases.append((name, lambda v=v: _capi.sincos_f32_variant(x, s, c, n, variant=v), None))
+    for nd, (ns, nc) in sorted(ABLATION_TERMS.items()):
+        ss, cc = taylor_series(nd, ns, nc)
+        cases.append(("doublings_%d_series_%d_%d" % (nd, ns, nc),
+                      lambda nd=nd, ss=ss, cc=cc: _capi.sincos_f32_doublings(x, s, c, nd, ss, cc, n),
+                      8 + ns + nc + 4 * nd))
+    times = {name: [] for name, _, _ in cases}
+    for _ in range(3):
+        for name, fn, _ in cases:
+            ms, _ = time_launches(torch, fn, reps, 3)
+            times[name].append(ms)
+    base = float(np.median(times["plain"]))
+    res = {"workload": "the roofline workload (%d angles); A/B rounds against the plain kernel, "
+                       "median of 3" % n}
+    for name, _, ops in cases[1:]:
+        ms = float(np.median(times[name]))
+        res[name] = {"kernel_ms": round(ms, 4), "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+                     "per_byte_vs_plain": round(base / ms, 4)}
+        if ops is not None:
+            res[name]["valu_ops_per_element_model"] = ops
     return res
 
 
@@ -429,7 +477,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceiling", action="store_true")
     ap.add_argument("--forms",
-                    default="variants,ragged,interleaved,adjoint,sinusoid,huygens,serve",
+                    default="variants,ablations,ragged,interleaved,adjoint,sinusoid,huygens,serve",
                     help="comma list of forms to measure after the plain kernel ('' = none)")
     args = ap.parse_args(argv)
 
@@ -543,10 +591,13 @@ def main(argv=None):
         if "variants" in forms:  # uses the roofline arrays, so before they are freed
             log("form: variants")
             out["forms"]["variants"] = bench_variants(torch, max(10, args.steps // 4), x, s, c)
+        if "ablations" in forms:  # also on the roofline arrays
+            log("form: ablations")
+            out["forms"]["ablations"] = bench_ablations(torch, max(10, args.steps // 4), x, s, c)
         del x, s, c
         torch.cuda.empty_cache()
     for f in forms:
-        if f == "variants":
+        if f in ("variants", "ablations"):
             continue
         log("form: %s" % f)
         if f == "ragged":

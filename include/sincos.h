@@ -262,6 +262,41 @@ SINCOS_API int sincos_pair_ceiling_f32(const float *x, float *out, int64_t n, in
                                        void *stream);
 
 /* ---------------------------------------------------------------------- */
+/* Ablations of Sec. II, for analysis and measurement.  Each element is
+ * reduced as in step 1, then:
+ *   sincos_f32_variant: the method's series (method 1 or 2) and one of
+ *     LISTING   the method itself (the plain form's bits);
+ *     NO_FIX    both doublings, no magnitude factor;
+ *     TEXT_FIX  both doublings, then the text's factor (3 - s^2 - c^2)/2
+ *               applied to the final pair (Sec. II, magnitude correction);
+ *     EQ2       both doublings with the rejected eq. (2),
+ *               cos 2a = 1 - 2 sin^2 a, and the method's factor.
+ *   sincos_f32_doublings: the general form of the trade-off in Sec. II
+ *     between series length and doublings: s1 = q (ss[0] + ss[1] q^2 + ...
+ *     + ss[ns-1] q^(2 ns - 2)), c1 = 1 + q^2 (cc[0] + ... + cc[nc-1]
+ *     q^(2 nc - 2)), by Horner in q^2, approximating sin and cos of
+ *     2 pi q / 2^ndoub; then ndoub eq. (1) doublings.  With fix, the pair is
+ *     scaled by 2 - s^2 - c^2 of the pair before the last doubling (for
+ *     ndoub = 0, by (3 - s^2 - c^2)/2 of the series pair).  ndoub = 2, the
+ *     first method's series and fix = 1 give the plain form's bits.
+ * arith: FUSED or SPLIT (CONTRACT is EINVAL).  ss, cc: HOST arrays of ns and
+ * nc binary32 coefficients (1 <= ns, nc <= 16), read before the call
+ * returns; 0 <= ndoub <= 8.  x, s, c: [n] device arrays, 16-byte aligned;
+ * the aliasing rules of the plain form.                                    */
+typedef enum {
+    SINCOS_VARIANT_LISTING = 0,
+    SINCOS_VARIANT_NO_FIX = 1,
+    SINCOS_VARIANT_TEXT_FIX = 2,
+    SINCOS_VARIANT_EQ2 = 3
+} sincos_variant_t;
+
+SINCOS_API int sincos_f32_variant(const float *x, float *s, float *c, int64_t n, int32_t arith,
+                                  int32_t method, int32_t variant, void *stream);
+SINCOS_API int sincos_f32_doublings(const float *x, float *s, float *c, int64_t n, int32_t arith,
+                                    int32_t ndoub, const float *ss, int32_t ns, const float *cc,
+                                    int32_t nc, int32_t fix, void *stream);
+
+/* ---------------------------------------------------------------------- */
 /* Request server: continuous batching of sine-cosine requests of any size.
  *
  * A scheduler thread owns an output arena in device memory and up to

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libmi355_sincos.so")
 OK, EINVAL, EOVERLAP, ENOMEM, EHIP, ENODEV, ECANCELED, EBUDGET = 0, -1, -2, -3, -4, -5, -6, -7
 ARITH_FUSED, ARITH_SPLIT, ARITH_CONTRACT = 0, 1, 2
 METHOD_NORMALIZED, METHOD_ARCTAN = 0, 1
+VARIANT_LISTING, VARIANT_NO_FIX, VARIANT_TEXT_FIX, VARIANT_EQ2 = 0, 1, 2, 3
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "EOVERLAP", -3: "ENOMEM", -4: "EHIP", -5: "ENODEV",
                 -6: "ECANCELED", -7: "EBUDGET"}
 
@@ -98,6 +99,10 @@ _SIGNATURES = {
     "sincos_copy_ceiling_f32": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(Launch), _P]),
     "sincos_f32_interleaved": (ctypes.c_int, [_P, _P, _I64, _I32, _P]),
     "sincos_pair_ceiling_f32": (ctypes.c_int, [_P, _P, _I64, _I32, _P]),
+    "sincos_f32_variant": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _I32, _I32, _P]),
+    "sincos_f32_doublings": (ctypes.c_int, [_P, _P, _P, _I64, _I32, _I32,
+                                            ctypes.POINTER(ctypes.c_float), _I32,
+                                            ctypes.POINTER(ctypes.c_float), _I32, _I32, _P]),
     "huygens_f32": (ctypes.c_int, [_P, _P, _I64, _P, _I32, ctypes.c_float, ctypes.c_float, _P, _P,
                                    _P]),
     "sincos_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)]),
@@ -243,6 +248,26 @@ def sincos_pair_ceiling_f32(x, out, n=None, reps=1, stream=None) -> None:
     n = _numel(x, n)
     _check(lib().sincos_pair_ceiling_f32(_ptr(x, n), _ptr(out, n), n, int(reps),
                                          _stream(stream)))
+
+
+def sincos_f32_variant(x, s, c, n=None, arith=ARITH_FUSED, method=METHOD_NORMALIZED,
+                       variant=VARIANT_LISTING, stream=None) -> None:
+    """One of the Sec. II ablations of the method (VARIANT_*)."""
+    n = _numel(x, n)
+    _check(lib().sincos_f32_variant(_ptr(x, n), _ptr(s, n), _ptr(c, n), n, int(arith),
+                                    int(method), int(variant), _stream(stream)))
+
+
+def sincos_f32_doublings(x, s, c, ndoub, ss, cc, n=None, arith=ARITH_FUSED, fix=True,
+                         stream=None) -> None:
+    """The general ablation: series ss, cc (host sequences of binary32
+    coefficients) for 2 pi q / 2^ndoub, then ndoub doublings."""
+    n = _numel(x, n)
+    ssa = (ctypes.c_float * max(len(ss), 1))(*[float(v) for v in ss])
+    cca = (ctypes.c_float * max(len(cc), 1))(*[float(v) for v in cc])
+    _check(lib().sincos_f32_doublings(_ptr(x, n), _ptr(s, n), _ptr(c, n), n, int(arith),
+                                      int(ndoub), ssa, len(ss), cca, len(cc), int(bool(fix)),
+                                      _stream(stream)))
 
 
 def _seg_tables(segs, lens):

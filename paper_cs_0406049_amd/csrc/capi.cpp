@@ -533,6 +533,69 @@ extern "C" int sincos_pair_ceiling_f32(const float *x, float *out, int64_t n, in
 }
 
 // ---------------------------------------------------------------------------
+// Ablations
+
+static int check_ablation_arrays(const float *x, float *s, float *c, int64_t n, int32_t arith,
+                                 const char *who)
+{
+    int rc = check_triplet(x, s, c, n, who);
+    if (rc != SINCOS_OK)
+        return rc;
+    if (arith != SINCOS_ARITH_FUSED && arith != SINCOS_ARITH_SPLIT)
+        return set_error(SINCOS_EINVAL, std::string(who) + ": arith must be FUSED or SPLIT");
+    const uintptr_t bits = reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(s) |
+                           reinterpret_cast<uintptr_t>(c);
+    if (n > 0 && (bits & 15) != 0)
+        return set_error(SINCOS_EINVAL, std::string(who) + ": x, s and c must be 16-byte aligned");
+    return SINCOS_OK;
+}
+
+extern "C" int sincos_f32_variant(const float *x, float *s, float *c, int64_t n, int32_t arith,
+                                  int32_t method, int32_t variant, void *stream)
+{
+    clear_error();
+    int rc = check_ablation_arrays(x, s, c, n, arith, "sincos_f32_variant");
+    if (rc != SINCOS_OK)
+        return rc;
+    if (method != SINCOS_METHOD_NORMALIZED && method != SINCOS_METHOD_ARCTAN)
+        return set_error(SINCOS_EINVAL, "sincos_f32_variant: method must be NORMALIZED or ARCTAN");
+    if (variant < SINCOS_VARIANT_LISTING || variant > SINCOS_VARIANT_EQ2)
+        return set_error(SINCOS_EINVAL, "sincos_f32_variant: unknown variant");
+    if (n == 0)
+        return SINCOS_OK;
+    const DeviceInfo *dev;
+    if ((rc = current_device(&dev)) != SINCOS_OK)
+        return rc;
+    hipError_t e = launch_variant(x, s, c, n, arith, method, variant, (hipStream_t)stream);
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "sincos_f32_variant: kernel launch");
+}
+
+extern "C" int sincos_f32_doublings(const float *x, float *s, float *c, int64_t n, int32_t arith,
+                                    int32_t ndoub, const float *ss, int32_t ns, const float *cc,
+                                    int32_t nc, int32_t fix, void *stream)
+{
+    clear_error();
+    int rc = check_ablation_arrays(x, s, c, n, arith, "sincos_f32_doublings");
+    if (rc != SINCOS_OK)
+        return rc;
+    if (ndoub < 0 || ndoub > kMaxDoublings)
+        return set_error(SINCOS_EINVAL, "sincos_f32_doublings: ndoub must be in [0, " +
+                                            std::to_string(kMaxDoublings) + "]");
+    if (!ss || !cc || ns < 1 || ns > kMaxSeriesTerms || nc < 1 || nc > kMaxSeriesTerms)
+        return set_error(SINCOS_EINVAL, "sincos_f32_doublings: need 1 to " +
+                                            std::to_string(kMaxSeriesTerms) +
+                                            " host coefficients in ss and in cc");
+    if (n == 0)
+        return SINCOS_OK;
+    const DeviceInfo *dev;
+    if ((rc = current_device(&dev)) != SINCOS_OK)
+        return rc;
+    hipError_t e = launch_doublings(x, s, c, n, arith, ndoub, ss, ns, cc, nc, fix,
+                                    (hipStream_t)stream);
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "sincos_f32_doublings: kernel launch");
+}
+
+// ---------------------------------------------------------------------------
 // Ragged form
 
 extern "C" int sincos_f32_ragged_ex(const sincos_seg_t *segs, const int64_t *lens, int32_t count,

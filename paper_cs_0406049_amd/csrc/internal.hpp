@@ -64,6 +64,16 @@ hipError_t launch_ragged(const RaggedDesc *desc, const int64_t *ubeg, int32_t co
                          int64_t total_units, int arith, int method, const LaunchShape &shape,
                          hipStream_t stream);
 
+// Ablations of Sec. II (ablation.hip): variant in SINCOS_VARIANT_*; the
+// general form with ndoub doublings after series of ns and nc terms.
+constexpr int kMaxSeriesTerms = 16;
+constexpr int kMaxDoublings = 8;
+hipError_t launch_variant(const float *x, float *s, float *c, int64_t n, int arith, int method,
+                          int variant, hipStream_t stream);
+hipError_t launch_doublings(const float *x, float *s, float *c, int64_t n, int arith, int ndoub,
+                            const float *ss, int ns, const float *cc, int nc, int fix,
+                            hipStream_t stream);
+
 // A small ragged table passed whole as a kernel argument (3.6 KB), so the
 // launch needs no staging copy: up to kInlineSegs non-empty segments.
 constexpr int kInlineSegs = 64;

@@ -304,3 +304,27 @@ def test_interleaved_validation(L):
     assert f(BASE + 48, BASE, 5, 1, None) == _capi.EOVERLAP
     rc = f(BASE, BASE + (1 << 44), (1 << 31) * 512, 0, None)
     assert rc == _capi.EINVAL and "too large" in _capi.last_error()
+
+
+def test_ablation_validation(L):
+    v = L.sincos_f32_variant
+    assert v(None, None, None, 0, 0, 0, 0, None) == _capi.OK
+    assert v(BASE, BASE + 4096, BASE + 8192, 4, 2, 0, 0, None) == _capi.EINVAL    # CONTRACT
+    assert v(BASE, BASE + 4096, BASE + 8192, 4, 0, 2, 0, None) == _capi.EINVAL    # method
+    assert v(BASE, BASE + 4096, BASE + 8192, 4, 0, 0, 4, None) == _capi.EINVAL    # variant
+    assert v(BASE + 4, BASE + 4100, BASE + 8196, 4, 0, 0, 0, None) == _capi.EINVAL  # 16-byte
+    assert v(BASE, BASE + 8, BASE + 8192, 4, 0, 0, 0, None) == _capi.EOVERLAP
+    d = L.sincos_f32_doublings
+    F = ctypes.c_float * 16
+    ss, cc = F(*([1.0] * 16)), F(*([-1.0] * 16))
+    args = lambda **k: dict(dict(x=BASE, s=BASE + 4096, c=BASE + 8192, n=4, arith=0, nd=2, ss=ss,  # noqa: E731
+                                 ns=4, cc=cc, nc=3, fix=1), **k)
+    call = lambda a: d(a["x"], a["s"], a["c"], a["n"], a["arith"], a["nd"], a["ss"], a["ns"],  # noqa: E731
+                       a["cc"], a["nc"], a["fix"], None)
+    assert call(args(nd=9)) == _capi.EINVAL and "ndoub" in _capi.last_error()
+    assert call(args(nd=-1)) == _capi.EINVAL
+    assert call(args(ns=0)) == _capi.EINVAL and call(args(nc=17)) == _capi.EINVAL
+    assert call(args(ss=None)) == _capi.EINVAL
+    assert call(args(arith=2)) == _capi.EINVAL
+    assert call(args(c=BASE + 4098)) == _capi.EINVAL
+    assert call(args(n=0, ss=None)) == _capi.EINVAL      # coefficients are checked first

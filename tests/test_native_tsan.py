@@ -28,7 +28,7 @@ SANITIZERS = {
 PROGRAMS = {"serve_stress": "serve_stress: ok", "host_paths": "host_paths: ok"}
 
 
-DEVICE_SOURCES = ("plain.hip", "forms.hip")   # kernels: built once, without a sanitizer
+DEVICE_SOURCES = ("plain.hip", "forms.hip", "ablation.hip")   # kernels: built once, no sanitizer
 
 
 def _hipcc():
@@ -40,7 +40,7 @@ def _hipcc():
 
 @pytest.fixture(scope="module")
 def device_objects(tmp_path_factory):
-    """The two sources that hold kernels, compiled once (their host side is
+    """The sources that hold kernels, compiled once (their host side is
     only launch stubs); the host-side sources are rebuilt per sanitizer."""
     out = tmp_path_factory.mktemp("devobj")
     objs = []
