@@ -451,6 +451,11 @@ def bench_serve(torch, plain_gelem_s):
             comp = srv.replay(xs, rs.sizes, arr)
             summ = serve.latency_summary(comp)
             summ["batches"] = srv.stats()["batches"]
+            # where the time goes: waiting to be launched, then on the device
+            summ["p50_submit_to_launch_us"] = float(
+                np.percentile((comp["t_launch_ns"] - comp["t_submit_ns"]) / 1e3, 50))
+            summ["p50_launch_to_complete_us"] = float(
+                np.percentile((comp["t_complete_ns"] - comp["t_launch_ns"]) / 1e3, 50))
         closed = None
         with serve.Server(mode=mode, max_inflight=4, auto_release=True) as srv:
             comp = srv.replay(xs, rs.sizes, np.zeros(rs.sizes.size, np.int64))
