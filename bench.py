@@ -308,7 +308,8 @@ def alu_roofline(tops, ops_per_pair, ceil):
 
 def bench_sinusoid(torch, reps):
     from paper_cs_0406049_amd import _capi, workloads
-    from paper_cs_0406049_amd.autograd import sinusoid_loss_and_grads
+    from paper_cs_0406049_amd.autograd import (sinusoid_loss_and_grads,
+                                               sinusoid_loss_and_grads_two_pass)
     p = workloads.sinusoid_problem()
     d = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
     t, A, w, phi, yobs = d(p.t), d(p.A), d(p.w), d(p.phi), d(p.y_obs)
@@ -324,6 +325,8 @@ def bench_sinusoid(torch, reps):
         t, r, A, w, phi, gA, gw, gp, ws, nb), reps, 2, ALU_WARM_MS)
     tot_ms, _ = time_launches(torch, lambda: sinusoid_loss_and_grads(t, yobs, A, w, phi), reps, 2,
                               ALU_WARM_MS)
+    two_ms, _ = time_launches(torch, lambda: sinusoid_loss_and_grads_two_pass(t, yobs, A, w, phi),
+                              reps, 2, ALU_WARM_MS)
     ceil = valu_ceiling(torch)
     # the same fit step captured as a HIP graph (no host work per step)
     side = torch.cuda.Stream()
@@ -357,6 +360,7 @@ def bench_sinusoid(torch, reps):
                         "1/2 sum (y - y_obs)^2, forward + adjoint" % (N, K),
             "forward_ms": round(f_ms, 4), "adjoint_ms": round(a_ms, 4),
             "loss_and_grads_ms": round(tot_ms, 4), "loss_and_grads_graph_ms": round(graph_ms, 4),
+            "loss_and_grads_two_pass_ms": round(two_ms, 4),
             "composed_plain_kernel_plus_torch_ms":
             round(c_ms, 4), "speedup_vs_composed": round(c_ms / tot_ms, 2),
             "pairs_per_s": round(2 * pairs / (tot_ms * 1e-3), 1),

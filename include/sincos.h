@@ -226,6 +226,23 @@ SINCOS_API int sinusoid_f32_backward(const float *t, const float *g, int64_t N, 
                           const float *w, const float *phi, int32_t K, float *gA, float *gw,
                           float *gphi, void *workspace, int64_t workspace_bytes, void *stream);
 
+/* One step of the least-squares fit in one pass: with y_i as
+ * sinusoid_f32_forward computes it and r_i = y_i - y_obs_i,
+ *     loss[0] = 1/2 sum_i r_i^2,
+ *     gA, gw, gphi = the gradients sinusoid_f32_backward gives for g = r
+ * (the same bits as sinusoid_f32_residual followed by sinusoid_f32_backward;
+ * the loss is summed in another fixed order, so its last bits may differ).
+ * The residual stays on chip.  workspace: device scratch of at least
+ * sinusoid_f32_fit_step_workspace_bytes(N, K) bytes ((3 * 64 ceil(K/64) + 1)
+ * ceil(N/2048) floats), owned by the caller.  loss, gA, gw, gphi and the
+ * workspace overlap neither each other nor t, y_obs, A, w, phi; all arrays
+ * 4-byte aligned.  N == 0 gives loss 0 and zero gradients.                 */
+SINCOS_API int64_t sinusoid_f32_fit_step_workspace_bytes(int64_t N, int32_t K);
+SINCOS_API int sinusoid_f32_fit_step(const float *t, const float *y_obs, int64_t N, const float *A,
+                                     const float *w, const float *phi, int32_t K, float *loss,
+                                     float *gA, float *gw, float *gphi, void *workspace,
+                                     int64_t workspace_bytes, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Huygens' principle point-source sum (the application named in Sec. IV):
  * the complex field at P screen points (xo_i, yo_i, L) from S point sources

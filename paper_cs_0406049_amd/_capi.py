@@ -96,6 +96,9 @@ _SIGNATURES = {
                                              _P]),
     "sinusoid_f32_backward": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _P, _P, _P, _P, _I64,
                                              _P]),
+    "sinusoid_f32_fit_step_workspace_bytes": (_I64, [_I64, _I32]),
+    "sinusoid_f32_fit_step": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _P, _P, _P, _P, _P,
+                                             _I64, _P]),
     "sincos_copy_ceiling_f32": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(Launch), _P]),
     "sincos_f32_interleaved": (ctypes.c_int, [_P, _P, _I64, _I32, _P]),
     "sincos_pair_ceiling_f32": (ctypes.c_int, [_P, _P, _I64, _I32, _P]),
@@ -379,6 +382,23 @@ def sinusoid_f32_backward(t, g, A, w, phi, gA, gw, gphi, workspace, workspace_by
     _check(lib().sinusoid_f32_backward(_ptr(t, N), _ptr(g, N), N, _ptr(A, K), _ptr(w, K),
                                        _ptr(phi, K), K, _ptr(gA, K), _ptr(gw, K), _ptr(gphi, K),
                                        _raw_ptr(workspace, int(workspace_bytes)),
+                                       int(workspace_bytes), _stream(stream)))
+
+
+def sinusoid_f32_fit_step_workspace_bytes(N: int, K: int) -> int:
+    return int(lib().sinusoid_f32_fit_step_workspace_bytes(int(N), int(K)))
+
+
+def sinusoid_f32_fit_step(t, y_obs, A, w, phi, loss, gA, gw, gphi, workspace,
+                          workspace_bytes=None, N=None, K=None, stream=None) -> None:
+    """loss[0] = 1/2 sum (y - y_obs)^2 and its gradients in one pass."""
+    N = _numel(t, N)
+    K = _numel(A, K)
+    if workspace_bytes is None:
+        workspace_bytes = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _check(lib().sinusoid_f32_fit_step(_ptr(t, N), _ptr(y_obs, N), N, _ptr(A, K), _ptr(w, K),
+                                       _ptr(phi, K), K, _ptr(loss, 1), _ptr(gA, K), _ptr(gw, K),
+                                       _ptr(gphi, K), _raw_ptr(workspace, int(workspace_bytes)),
                                        int(workspace_bytes), _stream(stream)))
 
 

@@ -84,8 +84,24 @@ def sinusoid(t, A, w, phi):
 
 def sinusoid_loss_and_grads(t, y_obs, A, w, phi):
     """L = 1/2 sum (y - y_obs)^2 and (dL/dA, dL/dw, dL/dphi) via the kernels,
-    without autograd bookkeeping: the forward kernel fused with the residual
-    and the loss, then the adjoint kernel.  L is a 0-dim float32 tensor."""
+    without autograd bookkeeping: one pass over the samples (forward model,
+    residual kept on chip, adjoint sums), then one reduction.  L is a 0-dim
+    float32 tensor; the gradients are the same bits as the forward kernel's
+    residual followed by the adjoint kernel."""
+    N, K = t.numel(), A.numel()
+    loss = torch.empty(1, dtype=torch.float32, device=t.device)
+    gA = torch.empty_like(A)
+    gw = torch.empty_like(w)
+    gphi = torch.empty_like(phi)
+    nb = _capi.sinusoid_f32_fit_step_workspace_bytes(N, K)
+    ws = torch.empty(max(nb, 4), dtype=torch.uint8, device=t.device)
+    _capi.sinusoid_f32_fit_step(t, y_obs, A, w, phi, loss, gA, gw, gphi, ws, nb, N, K)
+    return loss[0], gA, gw, gphi
+
+
+def sinusoid_loss_and_grads_two_pass(t, y_obs, A, w, phi):
+    """The same step as two library calls: the forward kernel fused with the
+    residual and the loss, then the adjoint kernel over the stored residual."""
     N, K = t.numel(), A.numel()
     r = torch.empty_like(t)
     loss = torch.empty(1, dtype=torch.float32, device=t.device)

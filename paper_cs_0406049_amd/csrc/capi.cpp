@@ -958,6 +958,54 @@ extern "C" int sinusoid_f32_backward(const float *t, const float *g, int64_t N, 
     return e == hipSuccess ? SINCOS_OK : hip_error(e, "sinusoid_f32_backward: kernel launch");
 }
 
+extern "C" int64_t sinusoid_f32_fit_step_workspace_bytes(int64_t N, int32_t K)
+{
+    if (N < 0 || K < 0)
+        return -1;
+    return sinusoid_fit_parts(N) * (3 * sinusoid_kgroups(K) * 64 + 1) * (int64_t)sizeof(float);
+}
+
+extern "C" int sinusoid_f32_fit_step(const float *t, const float *y_obs, int64_t N, const float *A,
+                                     const float *w, const float *phi, int32_t K, float *loss,
+                                     float *gA, float *gw, float *gphi, void *workspace,
+                                     int64_t workspace_bytes, void *stream)
+{
+    clear_error();
+    const char *who = "sinusoid_f32_fit_step";
+    if (N < 0)
+        return set_error(SINCOS_EINVAL, std::string(who) + ": N < 0");
+    if (sinusoid_fit_parts(N) > INT32_MAX)
+        return set_error(SINCOS_EINVAL, std::string(who) + ": N too large");
+    int rc = check_params(A, w, phi, K, who);
+    if (rc != SINCOS_OK)
+        return rc;
+    if (!loss || (K > 0 && (!gA || !gw || !gphi)))
+        return set_error(SINCOS_EINVAL, std::string(who) + ": null loss or gradient output");
+    if (N > 0 && (!t || !y_obs))
+        return set_error(SINCOS_EINVAL, std::string(who) + ": null t or y_obs with N > 0");
+    if (!all_aligned4({t, y_obs, A, w, phi, loss, gA, gw, gphi, workspace}))
+        return set_error(SINCOS_EINVAL, std::string(who) + ": pointers must be 4-byte aligned");
+    const int64_t need = sinusoid_f32_fit_step_workspace_bytes(N, K);
+    if (N > 0 && (!workspace || workspace_bytes < need))
+        return set_error(SINCOS_EINVAL, std::string(who) + ": workspace needs " +
+                                            std::to_string(need) + " bytes");
+    if ((rc = check_disjoint({{loss, 1, "loss"}, {gA, K, "gA"}, {gw, K, "gw"}, {gphi, K, "gphi"},
+                              {N > 0 ? workspace : nullptr, need / 4, "workspace"}},
+                             {{t, N, "t"}, {y_obs, N, "y_obs"}, {A, K, "A"}, {w, K, "w"},
+                              {phi, K, "phi"}},
+                             who)) != SINCOS_OK)
+        return rc;
+    const DeviceInfo *dev;
+    if ((rc = current_device(&dev)) != SINCOS_OK)
+        return rc;
+    float *part = static_cast<float *>(workspace);
+    const int64_t parts = sinusoid_fit_parts(N);
+    float *loss_part = part ? part + 3 * sinusoid_kgroups(K) * 64 * parts : nullptr;
+    hipError_t e = launch_sinusoid_fit(t, y_obs, N, A, w, phi, K, loss, gA, gw, gphi, part,
+                                       loss_part, (hipStream_t)stream);
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "sinusoid_f32_fit_step: kernel launch");
+}
+
 extern "C" int huygens_f32(const float *xo, const float *yo, int64_t P, const float *src,
                            int32_t S, float k, float L, float *re, float *im, void *stream)
 {

@@ -308,21 +308,28 @@ __device__ __forceinline__ float strided_sum(const float *p, int64_t n, int64_t 
     return acc;
 }
 
-// loss = 1/2 * (sum of the workgroup partials): one workgroup, strided
-// per-thread sums, then a fixed 256-way tree.
-__global__ void __launch_bounds__(256) k_loss_reduce(const float *part, int64_t nparts, float *loss)
+// Sum of row[0..n) by one 256-thread workgroup: strided per-thread sums,
+// then a fixed 256-way tree (the result is in red[0] for every thread after
+// the last barrier).
+__device__ __forceinline__ float block_sum_256(const float *row, int64_t n, float *red)
 {
-    __shared__ float red[256];
-    const float acc = strided_sum(part, nparts, threadIdx.x, 256);
-    red[threadIdx.x] = acc;
+    red[threadIdx.x] = strided_sum(row, n, threadIdx.x, 256);
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h)
             red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
     }
+    return red[0];
+}
+
+// loss = 1/2 * (sum of the workgroup partials): one workgroup.
+__global__ void __launch_bounds__(256) k_loss_reduce(const float *part, int64_t nparts, float *loss)
+{
+    __shared__ float red[256];
+    const float v = block_sum_256(part, nparts, red);
     if (threadIdx.x == 0)
-        loss[0] = 0.5f * red[0];
+        loss[0] = 0.5f * v;
 }
 
 // K5: sinusoid adjoint.  Lane <-> frequency k (a wave covers 64 of them),
@@ -395,16 +402,134 @@ __global__ void __launch_bounds__(256) k_sinusoid_reduce(const float *partial, i
     const int32_t k = blockIdx.x;
     const int j = blockIdx.y;  // 0: A, 1: phi, 2: w
     __shared__ float red[256];
-    const float *row = partial + ((int64_t)j * Kpad + k) * nparts;
-    red[threadIdx.x] = strided_sum(row, nparts, threadIdx.x, blockDim.x);
+    const float v = block_sum_256(partial + ((int64_t)j * Kpad + k) * nparts, nparts, red);
+    if (threadIdx.x == 0 && k < K) {
+        if (j == 0)
+            gA[k] = v;
+        else if (j == 1)
+            gphi[k] = A[k] * v;
+        else
+            gw[k] = A[k] * v;
+    }
+}
+
+// K5b: one step of the least-squares fit in one pass over the samples.  A
+// workgroup of kAdjWaves waves owns kAdjWaves * kAdjChunk consecutive
+// samples.  Phase 1, lane <-> sample: y_i as the forward model computes it,
+// r_i = y_i - y_obs_i, kept in LDS with t_i (the residual never goes to
+// HBM), and the workgroup's partial of sum r_i^2.  Phase 2, lane <->
+// frequency: exactly the adjoint kernel's sums over the same chunks in the
+// same order, with t_i and r_i read from LDS, and the same tree over the
+// waves.  The gradients are therefore the same bits as the forward kernel's
+// residual followed by the adjoint kernel.
+constexpr int kFitSamples = kAdjWaves * (int)kAdjChunk;  // 2048
+
+__global__ void __launch_bounds__(64 * kAdjWaves) k_sinusoid_fit(
+    const float *__restrict__ t, const float *__restrict__ y_obs, int64_t N,
+    const float *__restrict__ A, const float *__restrict__ w, const float *__restrict__ phi,
+    int32_t K, int32_t kgroups, float *partial, float *loss_part)
+{
+    __shared__ float ts[kFitSamples];
+    __shared__ float rs[kFitSamples];
+    __shared__ float sums[3][kAdjWaves][64];
+    __shared__ float red[64 * kAdjWaves];
+    const int64_t base = (int64_t)blockIdx.x * kFitSamples;
+    const int64_t nparts = gridDim.x;
+    const int32_t Kpad = kgroups * 64;
+
+    // phase 1: two samples per thread, the forward model in k order from +0
+    float sq = 0.0f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int li = (int)threadIdx.x + h * 64 * kAdjWaves;
+        const int64_t i = base + li;
+        float ti = 0.0f, r = 0.0f;
+        if (i < N) {
+            ti = t[i];
+            float acc = 0.0f;
+#pragma unroll 4
+            for (int32_t k = 0; k < K; ++k) {
+                float sv, cv;
+                sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(w[k], ti, phi[k]), sv, cv);
+                acc = __builtin_fmaf(A[k], sv, acc);
+            }
+            r = acc - y_obs[i];
+            sq = __builtin_fmaf(r, r, sq);
+        }
+        ts[li] = ti;
+        rs[li] = r;
+    }
+    red[threadIdx.x] = sq;
     __syncthreads();
-    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    for (int h = 64 * kAdjWaves / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h)
             red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
     }
+    if (threadIdx.x == 0)
+        loss_part[blockIdx.x] = red[0];
+
+    // phase 2: the adjoint sums, one k group of 64 frequencies at a time
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t i0 = base + (int64_t)wave * kAdjChunk;
+    const int64_t i1 = min(i0 + kAdjChunk, N);
+    for (int32_t kg = 0; kg < kgroups; ++kg) {
+        const int32_t k = kg * 64 + lane;
+        const bool active = k < K;
+        const float wk = active ? w[k] : 0.f;
+        const float pk = active ? phi[k] : 0.f;
+        float sa = 0.f, sp = 0.f, sw = 0.f;
+#pragma unroll 8
+        for (int64_t i = i0; i < i1; ++i) {
+            const float ti = ts[i - base], gi = rs[i - base];
+            float sv, cv;
+            sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(wk, ti, pk), sv, cv);
+            sa = __builtin_fmaf(gi, sv, sa);
+            sp = __builtin_fmaf(gi, cv, sp);
+            sw = __builtin_fmaf(gi * ti, cv, sw);
+        }
+        if (kg > 0)
+            __syncthreads();  // the previous group's tree has read sums
+        sums[0][wave][lane] = sa;
+        sums[1][wave][lane] = sp;
+        sums[2][wave][lane] = sw;
+        __syncthreads();
+        if (wave < 3) {
+            float v[kAdjWaves];
+#pragma unroll
+            for (int q = 0; q < kAdjWaves; ++q)
+                v[q] = sums[wave][q][lane];
+#pragma unroll
+            for (int h = kAdjWaves / 2; h > 0; h >>= 1)
+#pragma unroll
+                for (int q = 0; q < h; ++q)
+                    v[q] = v[q] + v[q + h];
+            partial[((int64_t)wave * Kpad + k) * nparts + blockIdx.x] = v[0];
+        }
+    }
+}
+
+// The fit step's reduction in one launch: blocks (k, j < 3) as
+// k_sinusoid_reduce, block (0, 3) the loss.
+__global__ void __launch_bounds__(256) k_fit_reduce(const float *partial, const float *loss_part,
+                                                    int64_t nparts, int32_t Kpad, int32_t K,
+                                                    const float *A, float *gA, float *gw,
+                                                    float *gphi, float *loss)
+{
+    const int32_t k = blockIdx.x;
+    const int j = blockIdx.y;
+    __shared__ float red[256];
+    if (j == 3) {
+        if (k != 0)
+            return;
+        const float v = block_sum_256(loss_part, nparts, red);
+        if (threadIdx.x == 0)
+            loss[0] = 0.5f * v;
+        return;
+    }
+    const float v = block_sum_256(partial + ((int64_t)j * Kpad + k) * nparts, nparts, red);
     if (threadIdx.x == 0 && k < K) {
-        const float v = red[0];
         if (j == 0)
             gA[k] = v;
         else if (j == 1)
@@ -749,6 +874,28 @@ hipError_t launch_sinusoid_backward(const float *t, const float *g, int64_t N, c
     }
     hipLaunchKernelGGL(k_sinusoid_reduce, dim3((unsigned)Kpad, 3), dim3(256), 0, st, partial,
                        nparts, Kpad, K, A, gA, gw, gphi);
+    return hipGetLastError();
+}
+
+int64_t sinusoid_fit_parts(int64_t N) { return (N + kFitSamples - 1) / kFitSamples; }
+
+hipError_t launch_sinusoid_fit(const float *t, const float *y_obs, int64_t N, const float *A,
+                               const float *w, const float *phi, int32_t K, float *loss,
+                               float *gA, float *gw, float *gphi, float *partial,
+                               float *loss_part, hipStream_t st)
+{
+    const int64_t nparts = sinusoid_fit_parts(N);
+    const int64_t kg = sinusoid_kgroups(K);
+    const int32_t Kpad = (int32_t)(kg * 64);
+    if (nparts > 0) {
+        hipLaunchKernelGGL(k_sinusoid_fit, dim3((unsigned)nparts), dim3(64 * kAdjWaves), 0, st, t,
+                           y_obs, N, A, w, phi, K, (int32_t)kg, partial, loss_part);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(k_fit_reduce, dim3((unsigned)Kpad, 4), dim3(256), 0, st, partial, loss_part,
+                       nparts, Kpad, K, A, gA, gw, gphi, loss);
     return hipGetLastError();
 }
 

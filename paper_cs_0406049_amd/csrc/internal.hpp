@@ -98,6 +98,13 @@ hipError_t launch_huygens(const float *xo, const float *yo, int64_t P, const flo
 int64_t sinusoid_chunks(int64_t N);
 int64_t sinusoid_parts(int64_t N);
 int64_t sinusoid_kgroups(int32_t K);
+// One fit step (forward, residual, loss and gradients): workgroup partials of
+// the gradients in partial[3][Kpad][parts], of the loss in loss_part[parts].
+int64_t sinusoid_fit_parts(int64_t N);
+hipError_t launch_sinusoid_fit(const float *t, const float *y_obs, int64_t N, const float *A,
+                               const float *w, const float *phi, int32_t K, float *loss,
+                               float *gA, float *gw, float *gphi, float *partial,
+                               float *loss_part, hipStream_t stream);
 hipError_t launch_sinusoid_backward(const float *t, const float *g, int64_t N, const float *A,
                                     const float *w, const float *phi, int32_t K, float *gA,
                                     float *gw, float *gphi, float *partial, hipStream_t stream);

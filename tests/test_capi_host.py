@@ -328,3 +328,31 @@ def test_ablation_validation(L):
     assert call(args(arith=2)) == _capi.EINVAL
     assert call(args(c=BASE + 4098)) == _capi.EINVAL
     assert call(args(n=0, ss=None)) == _capi.EINVAL      # coefficients are checked first
+
+
+def test_fit_step_validation_and_workspace(L):
+    wb = L.sinusoid_f32_fit_step_workspace_bytes
+    assert wb(-1, 4) == -1 and wb(4, -1) == -1
+    assert wb(0, 64) == 0
+    assert wb(4_194_304, 64) == 2048 * (3 * 64 + 1) * 4     # partials + loss partial per 2048 samples
+    assert wb(2049, 65) == 2 * (3 * 128 + 1) * 4
+    f = L.sinusoid_f32_fit_step
+    t, yo, A, w, p = BASE, BASE + 65536, BASE + 2 * 65536, BASE + 3 * 65536, BASE + 4 * 65536
+    loss, gA, gw, gp, ws = (BASE + k * 65536 for k in range(5, 10))
+    need = wb(16, 8)
+    ok = dict(t=t, yo=yo, N=16, A=A, w=w, p=p, K=8, loss=loss, gA=gA, gw=gw, gp=gp, ws=ws, wsb=need)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["t"], a["yo"], a["N"], a["A"], a["w"], a["p"], a["K"], a["loss"], a["gA"],
+                 a["gw"], a["gp"], a["ws"], a["wsb"], None)
+    assert call(N=-1) == _capi.EINVAL
+    assert call(loss=None) == _capi.EINVAL
+    assert call(yo=None) == _capi.EINVAL
+    assert call(wsb=need - 4) == _capi.EINVAL and "workspace" in _capi.last_error()
+    assert call(gA=A) == _capi.EOVERLAP                  # gradient into a parameter
+    assert call(loss=gw + 4) == _capi.EOVERLAP           # loss inside gw
+    assert call(ws=yo) == _capi.EOVERLAP                 # workspace over y_obs
+    assert call(gp=gp + 2) == _capi.EINVAL               # misaligned
+    rc = f(t, yo, (1 << 31) * 2048 + 1, A, w, p, 8, loss, gA, gw, gp, ws, 1 << 40, None)
+    assert rc == _capi.EINVAL and "too large" in _capi.last_error()

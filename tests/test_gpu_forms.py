@@ -386,6 +386,69 @@ def test_sinusoid_residual_and_loss(torch_dev, N, K):
     assert_bit_exact(td2.cpu().numpy(), r_or, "residual in place over t N=%d" % N)
 
 
+@pytest.mark.parametrize("N,K", [(1, 1), (2047, 3), (2048, 64), (4099, 64), (300000, 64),
+                                 (5000, 130), (3000, 0), (0, 5)])
+def test_fit_step_matches_the_two_pass_path(torch_dev, N, K):
+    """The one-pass fit step gives the same gradient bits as the forward
+    kernel's residual followed by the adjoint kernel, and a loss within the
+    rounding bound of its own fixed-order sums of the oracle's residual."""
+    torch = torch_dev
+    from paper_cs_0406049_amd import _capi
+    t, A, w, phi = _sinusoid_small(N, K, 3 * N + K + 1)
+    yobs = np.random.default_rng(N + 7).standard_normal(N).astype(np.float32)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda() if a.size else torch.empty(0, device="cuda")  # noqa: E731
+    td, Ad, wd, pd, yd = d(t), d(A), d(w), d(phi), d(yobs)
+    Kk = max(K, 1)
+    g1 = [torch.full((Kk,), float("nan"), device="cuda") for _ in range(3)]
+    loss1 = torch.full((1,), float("nan"), device="cuda")
+    nb = _capi.sinusoid_f32_fit_step_workspace_bytes(N, K)
+    ws = torch.empty(max(nb, 4), dtype=torch.uint8, device="cuda")
+    _capi.sinusoid_f32_fit_step(td, yd, Ad, wd, pd, loss1, *g1, ws, nb, N=N, K=K)
+    # the two-pass path
+    r = torch.empty(max(N, 1), device="cuda")
+    loss2 = torch.empty(1, device="cuda")
+    g2 = [torch.full((Kk,), float("nan"), device="cuda") for _ in range(3)]
+    nb_r = _capi.sinusoid_f32_residual_workspace_bytes(N)
+    nb_b = _capi.sinusoid_f32_backward_workspace_bytes(N, K)
+    ws2 = torch.empty(max(nb_r, nb_b, 4), dtype=torch.uint8, device="cuda")
+    _capi.sinusoid_f32_residual(td, yd, Ad, wd, pd, r, loss2, ws2, nb_r, N, K)
+    if K > 0:
+        _capi.sinusoid_f32_backward(td, r, Ad, wd, pd, *g2, ws2, nb_b, N, K)
+    torch.cuda.synchronize()
+    for a, b, name in zip(g1, g2, ("gA", "gw", "gphi")):
+        if K > 0:
+            assert torch.equal(a[:K].view(torch.int32), b[:K].view(torch.int32)), (name, N, K)
+    y_or = oracle.sinusoid_forward(t, A, w, phi, threads=oracle.default_threads()) if K and N else \
+        np.zeros(N, np.float32)
+    r_or = (y_or - yobs).astype(np.float32).astype(np.float64)
+    sq = r_or ** 2
+    exact = 0.5 * float(sq.sum())
+    depth = 2 + 10 + -(-max(1, -(-N // 2048)) // 256) + 8 + 2
+    assert abs(float(loss1.cpu()[0]) - exact) <= depth * U * 0.5 * float(sq.sum()) * 1.001 + 0.0, (N, K)
+    if N == 0:
+        assert float(loss1.cpu()[0]) == 0.0
+
+
+def test_fit_step_deterministic(torch_dev):
+    torch = torch_dev
+    from paper_cs_0406049_amd import _capi
+    t, A, w, phi = _sinusoid_small(100000, 64, 19)
+    yobs = np.random.default_rng(5).standard_normal(t.size).astype(np.float32)
+    d = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+    args = [d(t), d(yobs), d(A), d(w), d(phi)]
+    nb = _capi.sinusoid_f32_fit_step_workspace_bytes(t.size, A.size)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    outs = []
+    for _ in range(3):
+        o = [torch.empty(1, device="cuda")] + [torch.empty(64, device="cuda") for _ in range(3)]
+        _capi.sinusoid_f32_fit_step(*args, *o, ws, nb)
+        torch.cuda.synchronize()
+        outs.append([v.cpu() for v in o])
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
 def test_sinusoid_residual_empty(torch_dev):
     torch = torch_dev
     from paper_cs_0406049_amd import _capi
