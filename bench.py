@@ -210,6 +210,24 @@ def bench_variants(torch, reps, x, s, c):
         gbs = BYTES_PER_ELEM * n / (ms * 1e-3) / 1e9
         res[name] = {"kernel_ms": round(ms, 4), "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
                      "GBps": round(gbs, 1), "per_byte_vs_plain": round(base / ms, 4)}
+    # one GPU's share if the plain form were split over 8 GPUs: n/8 angles.
+    # Successive launches take the 8 shards in turn, so none re-reads data a
+    # previous launch left in the 256 MB cache (a shard's traffic is 400 MB).
+    m = n // 8
+    views = [(x[k * m:(k + 1) * m], s[k * m:(k + 1) * m], c[k * m:(k + 1) * m]) for k in range(8)]
+    turn = [0]
+
+    def next_shard():
+        xv, sv, cv = views[turn[0] % 8]
+        turn[0] += 1
+        _capi.sincos_f32(xv, sv, cv, m)
+    shard = []
+    for _ in range(3):
+        shard.append(time_launches(torch, next_shard, 8 * reps, 8)[0])
+    ms = float(np.median(shard))
+    res["shard_of_8"] = {"n": m, "kernel_ms": round(ms, 4),
+                         "gelem_s": round(m / (ms * 1e-3) / 1e9, 2),
+                         "per_byte_vs_plain": round(base / (8 * ms), 4)}
     return res
 
 
