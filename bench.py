@@ -234,16 +234,6 @@ def bench_variants(torch, reps, x, s, c):
 ABLATION_TERMS = {0: (6, 6), 1: (5, 4), 2: (4, 3), 3: (3, 3), 4: (3, 2), 5: (2, 2)}
 
 
-def taylor_series(ndoub, ns, nc):
-    """Taylor coefficients of sin and cos of a q, a = 2 pi / 2^ndoub, in the
-    form the doublings kernel takes (s1 = q (ss0 + ss1 q^2 + ...), c1 = 1 +
-    q^2 (cc0 + cc1 q^2 + ...)).  The timing does not depend on the values."""
-    a = 2.0 * math.pi / 2.0 ** ndoub
-    ss = [(-1) ** k * a ** (2 * k + 1) / math.factorial(2 * k + 1) for k in range(ns)]
-    cc = [(-1) ** (k + 1) * a ** (2 * k + 2) / math.factorial(2 * k + 2) for k in range(nc)]
-    return ss, cc
-
-
 def bench_ablations(torch, reps, x, s, c):
     """The Sec. II ablations over the roofline arrays, in A/B rounds against
     the plain kernel: the method without its fix, with the text's fix, with
@@ -251,6 +241,7 @@ def bench_ablations(torch, reps, x, s, c):
     the ablation table uses.  All move 12 bytes per element."""
     import numpy as np
     from paper_cs_0406049_amd import _capi
+    from paper_cs_0406049_amd.workloads import taylor_series
     n = x.numel()
     cases = [("plain", lambda: _capi.sincos_f32(x, s, c, n), None)]
     for name, v in (("no_fix", _capi.VARIANT_NO_FIX), ("text_fix", _capi.VARIANT_TEXT_FIX),

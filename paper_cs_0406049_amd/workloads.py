@@ -1,7 +1,8 @@
 """Seeded synthetic inputs for every workload of this package.
 
 This module holds input generation only: random angles, lengths, sample
-times, parameters and arrival times.  It contains none of the sine-cosine
+times, parameters, arrival times, and the series coefficients given to the
+general-doubling ablation.  It contains none of the sine-cosine
 method's arithmetic, so both the GPU path and the CPU oracle can consume what
 it makes without sharing any of the method's code.
 
@@ -131,6 +132,21 @@ def request_stream(count: int = 10_000, lo: float = 1e3, hi: float = 1e7, seed: 
     offsets = (rng.integers(0, np.maximum(slots, 0) + 1) * 64).astype(np.int64)
     pool = rng.uniform(-1e3, 1e3, pool_elems).astype(np.float32)
     return RequestStream(sizes, gaps, offsets, pool)
+
+
+# ---------------------------------------------------------------------------
+# Series for the general-doubling ablation
+
+
+def taylor_series(ndoub: int, ns: int, nc: int):
+    """Binary32 Taylor coefficients of sin and cos of a q, a = 2 pi / 2^ndoub,
+    in the form the general-doubling ablation takes: s1 = q (ss[0] + ss[1] q^2
+    + ...), c1 = 1 + q^2 (cc[0] + cc[1] q^2 + ...).  Any coefficients serve
+    for timing and for comparing two implementations bit for bit."""
+    a = 2.0 * math.pi / 2.0 ** ndoub
+    ss = [(-1) ** k * a ** (2 * k + 1) / math.factorial(2 * k + 1) for k in range(ns)]
+    cc = [(-1) ** (k + 1) * a ** (2 * k + 2) / math.factorial(2 * k + 2) for k in range(nc)]
+    return np.array(ss).astype(np.float32), np.array(cc).astype(np.float32)
 
 
 # ---------------------------------------------------------------------------

@@ -1,14 +1,14 @@
 """The Sec. II ablations on the GPU (sincos_f32_variant, sincos_f32_doublings)
 against the oracle's ablations, bit for bit: the method's alternatives (no
 fix, the text's fix, the eq. (2) doubling) in both arithmetics and methods,
-and the general form with n = 0..5 doublings after refitted series, with and
+and the general form with n = 0..5 doublings after Taylor series, with and
 without the fix.  The listing variant and the general form with n = 2, the
 printed series and the fix give the plain form's bits."""
 import numpy as np
 import pytest
 
 import oracle
-from oracle.series_fit import fit_series
+from paper_cs_0406049_amd.workloads import taylor_series
 from gpu_util import assert_bit_exact, lib_loaded
 
 pytestmark = pytest.mark.gpu
@@ -73,7 +73,7 @@ def test_variants_bit_exact(torch_dev, angles, arith, method, variant):
 def test_doublings_bit_exact(torch_dev, angles, arith, ndoub, fix):
     from paper_cs_0406049_amd import _capi
     x, xd = angles
-    ss, cc = fit_series(ndoub, *TERMS[ndoub])
+    ss, cc = taylor_series(ndoub, *TERMS[ndoub])
     s, c = _run(torch_dev, lambda a, b, d: _capi.sincos_f32_doublings(a, b, d, ndoub, ss, cc,
                                                                       arith=arith, fix=fix), xd)
     so, co = oracle.sincos_general(x, ndoub, ss, cc, arith, fix=fix,
@@ -100,7 +100,7 @@ def test_tails_and_in_place(torch_dev):
     torch = torch_dev
     from paper_cs_0406049_amd import _capi
     rng = np.random.default_rng(5)
-    ss, cc = fit_series(3, 3, 3)
+    ss, cc = taylor_series(3, 3, 3)
     for n in range(10):
         xh = rng.uniform(-50, 50, n).astype(np.float32)
         for variant in (1, 3):

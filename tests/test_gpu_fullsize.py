@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.series_fit import fit_series
+from paper_cs_0406049_amd.workloads import taylor_series
 from gpu_util import assert_bit_exact, lib_loaded, log
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -83,7 +83,7 @@ def test_ablations_roofline_workload_sampled(torch_dev, roofline, case):
     c = torch.empty_like(x)
     if case.startswith("doublings"):
         nd = int(case.split("_")[1])
-        ss, cc = fit_series(nd, *{0: (6, 6), 5: (2, 2)}[nd])
+        ss, cc = taylor_series(nd, *{0: (6, 6), 5: (2, 2)}[nd])
         _capi.sincos_f32_doublings(x, s, c, nd, ss, cc, n)
         idx = _sample(n, nd)
         so, co = oracle.sincos_general(xh[idx], nd, ss, cc)
