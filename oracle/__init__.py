@@ -74,6 +74,7 @@ def lib():
             L.oracle_reduce_f32.argtypes = [fp, fp, i64]
             L.oracle_quarter_series.argtypes = [ctypes.c_float, c_int, c_int, fp, fp]
             L.oracle_double_angle.argtypes = [ctypes.c_float, ctypes.c_float, c_int, fp, fp]
+            L.oracle_double_angle_eq2.argtypes = L.oracle_double_angle.argtypes
             L.oracle_magnitude_factor.restype = ctypes.c_float
             L.oracle_magnitude_factor.argtypes = [ctypes.c_float, ctypes.c_float, c_int, c_int]
             L.oracle_error_scan_reduced.argtypes = [u32, u32, u32, c_int, c_int, c_int, c_int,
@@ -195,6 +196,14 @@ def error_scan_variant(bits_lo: int, bits_hi: int, stride: int = 1, arith: int =
         raise ValueError("oracle_error_scan_variant failed")
     return dict(max_vec=mv.value, rms_vec=rv.value, max_amp=ma.value, argmax_vec=av.value,
                 argmax_amp=aa.value, count=cnt.value)
+
+
+def double_angle_eq2(s: float, c: float, arith: int = FUSED):
+    """One doubling with the rejected eq. (2), cos 2u = 1 - 2 sin^2 u (ablation)."""
+    so, co = ctypes.c_float(), ctypes.c_float()
+    lib().oracle_double_angle_eq2(ctypes.c_float(s), ctypes.c_float(c), arith, ctypes.byref(so),
+                                  ctypes.byref(co))
+    return np.float32(so.value), np.float32(co.value)
 
 
 def pair_variant(q1: float, arith: int = FUSED, method: int = METHOD1,

@@ -152,34 +152,103 @@ def _msub_from(a, b, c, fused):
     return fma(neg(a), b, c) if fused else sub(c, mul(a, b))
 
 
+def _series(xr: F32, sin_coef, cos_coef, fused):
+    """x * (sin_coef[0] + sin_coef[1] x^2 + ...), cos_coef[0] + cos_coef[1] x^2 + ...,
+    by Horner's rule in x^2, highest power first."""
+    x2 = mul(xr, xr)
+    t = sin_coef[-1]
+    for k in reversed(sin_coef[:-1]):
+        t = _madd(x2, t, k, fused)
+    u = cos_coef[-1]
+    for k in reversed(cos_coef[:-1]):
+        u = _madd(x2, u, k, fused)
+    return mul(xr, t), u
+
+
+def _reduce(x: float) -> F32:
+    turns = mul(F32.from_float(x), reduction_constant())
+    return sub(turns, rint(turns))
+
+
+def _double(s, c, fused):
+    """eq. (1)."""
+    return mul(F32(Fraction(2)), mul(s, c)), _msub_from(s, s, mul(c, c), fused)
+
+
+def _double_eq2(s, c, fused):
+    """The rejected eq. (2): cos 2u = 1 - 2 sin^2 u."""
+    two = F32(Fraction(2))
+    return mul(two, mul(s, c)), _msub_from(mul(two, s), s, F32(Fraction(1)), fused)
+
+
+def _factor(s, c, fused, method):
+    """2 - |p|^2 (method 1) or 1 / |p|^2 (method 2)."""
+    if method == 0:
+        return _msub_from(s, s, _msub_from(c, c, F32(Fraction(2)), fused), fused)
+    d = _madd(s, s, mul(c, c), fused)
+    return round_binary32(Fraction(1) / d.v, False)
+
+
+def _text_factor(s, c, fused):
+    """(3 - s^2 - c^2) / 2."""
+    h = _msub_from(s, s, _msub_from(c, c, F32(Fraction(3)), fused), fused)
+    return mul(F32(Fraction(1, 2)), h)
+
+
+def _method_series(method):
+    k = {n: c32(v) for n, v in METHOD_DECIMALS[method].items()}
+    return ([k["ss1"], k["ss2"], k["ss3"], k["ss4"]],
+            [F32(Fraction(1)), k["cc1"], k["cc2"], k["cc3"]])
+
+
 def pair(x: float, fused: bool = True, method: int = 0):
     """(s, c) bits of the pair of angle x, reading of the compiled oracle."""
-    k = {n: c32(v) for n, v in METHOD_DECIMALS[method].items()}
-    one, two = F32(Fraction(1)), F32(Fraction(2))
-    xv = F32.from_float(x)
-    x1 = mul(xv, reduction_constant())
-    q1 = sub(x1, rint(x1))
-    q2 = mul(q1, q1)
-    t = _madd(q2, k["ss4"], k["ss3"], fused)
-    t = _madd(q2, t, k["ss2"], fused)
-    t = _madd(q2, t, k["ss1"], fused)
-    s = mul(q1, t)
-    u = _madd(q2, k["cc3"], k["cc2"], fused)
-    u = _madd(q2, u, k["cc1"], fused)
-    c = _madd(q2, u, one, fused)
-    pairs = []
-    for _ in range(2):
-        c_new = _msub_from(s, s, mul(c, c), fused)
-        s_new = mul(two, mul(s, c))
-        pairs.append((s_new, c_new))
-        s, c = s_new, c_new
-    s2, c2 = pairs[0]
-    if method == 0:
-        m = _msub_from(s2, s2, _msub_from(c2, c2, two, fused), fused)
-    else:
-        d = _madd(s2, s2, mul(c2, c2), fused)
-        m = round_binary32(Fraction(1) / d.v, False)
+    s, c = _series(_reduce(x), *_method_series(method), fused)
+    s, c = _double(s, c, fused)
+    m = _factor(s, c, fused, method)
+    s, c = _double(s, c, fused)
     return mul(s, m).bits(), mul(c, m).bits()
+
+
+def variant(xr: float, fused: bool, method: int, which: str):
+    """(s, c) bits of an ablation on the reduced angle xr: "no_fix", "text_fix"
+    (the text's factor on the final pair) or "eq2" (both doublings with
+    eq. (2), the method's factor read after the first)."""
+    s, c = _series(F32.from_float(xr), *_method_series(method), fused)
+    dbl = _double_eq2 if which == "eq2" else _double
+    s1, c1 = dbl(s, c, fused)
+    s2, c2 = dbl(s1, c1, fused)
+    if which == "no_fix":
+        return s2.bits(), c2.bits()
+    m = _text_factor(s2, c2, fused) if which == "text_fix" else _factor(s1, c1, fused, method)
+    return mul(s2, m).bits(), mul(c2, m).bits()
+
+
+def pair_general(xr: float, ndoub: int, ss, cc, fused: bool, fix: bool):
+    """(s, c) bits of the general ablation on the reduced angle xr: series with
+    coefficients ss (sine, times x) and 1 + x^2 * cc (cosine), then ndoub
+    eq. (1) doublings; with fix, the factor 2 - |p|^2 read before the last
+    doubling, or (3 - |p|^2)/2 on the series pair when ndoub == 0."""
+    xv = F32.from_float(xr)
+    x2 = mul(xv, xv)
+    t = F32.from_float(float(ss[-1]))
+    for k in reversed(ss[:-1]):
+        t = _madd(x2, t, F32.from_float(float(k)), fused)
+    s = mul(xv, t)
+    u = F32.from_float(float(cc[-1]))
+    for k in reversed(cc[:-1]):
+        u = _madd(x2, u, F32.from_float(float(k)), fused)
+    c = _madd(x2, u, F32(Fraction(1)), fused)
+    m = None
+    if ndoub == 0 and fix:
+        m = _text_factor(s, c, fused)
+    for d in range(ndoub):
+        if fix and d == ndoub - 1:
+            m = _factor(s, c, fused, 0)
+        s, c = _double(s, c, fused)
+    if fix:
+        return mul(s, m).bits(), mul(c, m).bits()
+    return s.bits(), c.bits()
 
 
 def pair_altivec_form(x: float, method: int = 0):

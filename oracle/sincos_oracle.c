@@ -8,38 +8,67 @@
  * shares no code, header, table or constant with it; its constants are typed
  * here again from the paper's decimals.
  *
- * What it computes, one element at a time, in binary32 with round-to-nearest
- * and IEEE subnormals, in the order the paper gives the steps:
- *   1. scale the angle by 1/(2 pi) and reduce it modulo 1 by rounding to the
- *      nearest integer and subtracting (Sec. II, opening paragraph);
- *   2. the odd series for sin and the even series for cos of the quarter
- *      angle, Horner in q^2 (Sec. II, polynomials of method 1 and method 2);
- *   3. two angle doublings with the stable form, eq. (1);
- *   4. the magnitude correction (Sec. II, discussion after the stability
- *      analysis).  The factor is taken after the first doubling and applied
- *      to the final pair, as the sample implementation of Fig. 1 does:
- *      method 1 uses 2 - s^2 - c^2, method 2 the reciprocal of s^2 + c^2.
+ * The method as Sec. II states it, and as this file computes it, one element
+ * at a time, in binary32 with round-to-nearest and IEEE subnormals:
+ *
+ *   Reduction.  The angle theta is multiplied by 1/(2 pi) and reduced modulo
+ *   1 by rounding to the nearest integer and subtracting, which leaves the
+ *   fraction of a turn x in [-1/2, 1/2] (the subtraction is exact).
+ *
+ *   Series.  Power series give the sine and the cosine of a quarter of the
+ *   reduced angle, 2 pi x / 4: an odd polynomial in x for the sine, an even
+ *   one for the cosine, both evaluated by Horner's rule in x^2.  The first
+ *   method's coefficients are a least-squares fit of sine and cosine, the
+ *   second method's a fit of the angle alone (Sec. II, two coefficient sets).
+ *
+ *   Doubling.  Two angle doublings with eq. (1), sin 2u = 2 sin u cos u and
+ *   cos 2u = cos^2 u - sin^2 u, carry the quarter angle to the whole circle.
+ *   The stability analysis of Sec. II shows what one doubling does to a pair
+ *   with magnitude a and angle error d: (a sin(u+d), a cos(u+d)) becomes
+ *   (a^2 sin 2(u+d), a^2 cos 2(u+d)).  The relative angle error survives
+ *   unchanged; only the magnitude is squared.  (The rejected eq. (2) uses
+ *   cos 2u = 1 - 2 sin^2 u instead, which gives a^2 cos 2(u+d) + (1 - a^2):
+ *   the magnitude error leaks into the angle.  It is kept as an ablation.)
+ *
+ *   Magnitude.  After n doublings the magnitude is a^(2^n).  The magnitude
+ *   squared of the pair before the last doubling is that same number, so
+ *   with |p|^2 = 1 + e read there, the final pair is rescaled by 1/(1 + e):
+ *   to first order 1 - e = 2 - |p|^2 (first method, whose series keep e
+ *   tiny), or the exact reciprocal 1/|p|^2 (second method, whose series do
+ *   not).  Reading the factor one doubling early lets it be formed beside
+ *   the last doubling instead of after it; the paper's sample implementation
+ *   (Fig. 1) does the same, and the accuracy figures printed in Sec. II,
+ *   which the tests pin, come from it.  The text's own form, (3 - s^2 - c^2)
+ *   / 2 on the final pair, agrees to first order in e and is an ablation.
  *
  * Two arithmetic modes, selected per call:
- *   ORACLE_FUSED  each multiply-add of the AltiVec form of Fig. 1 is one fused
- *                 operation with a single rounding (C99 fmaf);
- *   ORACLE_SPLIT  the same expression tree with every product and every sum
+ *   ORACLE_FUSED  every product that feeds a sum is fused into it, one
+ *                 rounding (C99 fmaf), as on the paper's vector unit, which
+ *                 has only fused multiply-add.  In a sum of two products
+ *                 (c^2 - s^2, 2 - c^2 - s^2, s^2 + c^2) the cosine's square
+ *                 is the inner term: rounded on its own in c^2 - s^2 and
+ *                 s^2 + c^2, fused with the 2 in 2 - c^2 - s^2; the sine's
+ *                 square is fused last.  This is the placement of Fig. 1,
+ *                 the one the printed accuracy figures were measured with.
+ *   ORACLE_SPLIT  the same expressions with every product and every sum
  *                 rounded on its own.  This file must be compiled with
  *                 -ffp-contract=off so that the compiler fuses nothing.
  *
  * Readings where the paper leaves a choice open:
- *   - The listing adds +0.0 to every plain product because AltiVec has no
- *     plain multiply.  Here a product is a product.  The two differ only in
- *     the sign of an exact-zero result; the reduced angle below is never -0
- *     (x1 - rint(x1) with round-to-nearest gives +0), so the pair is the same.
- *   - rint() rounds ties to even, as vec_round does; q1 lies in [-1/2, 1/2].
+ *   - A vector unit without a plain multiply writes a product as a
+ *     multiply-add with a +0.0 addend.  Here a product is a product.  The
+ *     two differ only in the sign of an exact-zero result; the reduced angle
+ *     below is never -0 (x - rint(x) with round-to-nearest gives +0), so the
+ *     pair is the same.
+ *   - rint() rounds ties to even, as the vector unit's round does; the
+ *     reduced angle lies in [-1/2, 1/2].
  *   - The negative multiply-subtract c - a*b is IEEE fusedMultiplyAdd(-a,b,c)
  *     in the fused mode; its exact-zero result is +0.
  *   - Method 2's coefficient ss2 is the value printed in the text of Sec. II
- *     (-0.6466386936); the listing's -0.6466386396 is taken as a typo.
+ *     (-0.6466386936); Fig. 1's -0.6466386396 is taken as a typo.
  *   - Method 2's reciprocal is the correctly rounded 1.0f / d.
- *   - Inputs with |x| >= 2^23 / (1/(2 pi)) reduce to q1 = 0 and give (0, 1);
- *     +-Inf and NaN give (NaN, NaN).  Nothing here special-cases them.
+ *   - Inputs with |theta| >= 2^23 / (1/(2 pi)) reduce to x = 0 and give
+ *     (0, 1); +-Inf and NaN give (NaN, NaN).  Nothing special-cases them.
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -fPIC -shared
  *        -pthread sincos_oracle.c -lm
@@ -59,17 +88,17 @@
 
 /* ---------------------------------------------------------------------- */
 /* Constants: the paper's decimals, each read as a C double and rounded to
- * binary32 once, as the (vector float)(double) casts of Fig. 1 do.         */
+ * binary32 once.                                                           */
 
 static float reduction_constant(void)
 {
-    /* 1/(2 pi) with pi written to ten decimals (Fig. 1). */
+    /* 1/(2 pi) with pi written to ten decimals, as the paper writes it. */
     return (float)(1.0 / (2.0 * 3.1415926536));
 }
 
 struct series_coeffs {
-    float ss1, ss2, ss3, ss4; /* sin(pi q / 2) = q (ss1 + ss2 q^2 + ss3 q^4 + ss4 q^6) */
-    float cc1, cc2, cc3;      /* cos(pi q / 2) = 1 + cc1 q^2 + cc2 q^4 + cc3 q^6       */
+    float ss1, ss2, ss3, ss4; /* sin(pi x / 2) = x (ss1 + ss2 x^2 + ss3 x^4 + ss4 x^6) */
+    float cc1, cc2, cc3;      /* cos(pi x / 2) = 1 + cc1 x^2 + cc2 x^4 + cc3 x^6       */
 };
 
 static struct series_coeffs method_coeffs(int method)
@@ -116,129 +145,145 @@ static float mul_sub_from(float a, float b, float c, int arith)
     return c - p;
 }
 
-/* ---------------------------------------------------------------------- */
-/* Step 1 (Sec. II): x1 = x / (2 pi); q1 = x1 - nearest integer to x1.
- * The subtraction is exact (Sterbenz), so both modes agree.               */
-float oracle_reduce(float x)
+/* Horner's rule in x2 over coef[0..n-1], highest power first:
+ * coef[0] + coef[1] x2 + ... + coef[n-1] x2^(n-1).                         */
+static float horner(float x2, const float *coef, int n, int arith)
 {
-    float x1 = x * reduction_constant();
-    float r = rintf(x1);
-    return x1 - r;
+    float p = coef[n - 1];
+    for (int k = n - 2; k >= 0; k--)
+        p = mul_add(x2, p, coef[k], arith);
+    return p;
 }
 
-/* Step 2 (Sec. II polynomials): s1 ~ sin(pi q1 / 2), c1 ~ cos(pi q1 / 2). */
-void oracle_quarter_series(float q1, int arith, int method, float *s1, float *c1)
+/* ---------------------------------------------------------------------- */
+/* Reduction (Sec. II): the fraction of a turn, theta / (2 pi) less the
+ * nearest integer.  The subtraction is exact (Sterbenz), so both arithmetic
+ * modes agree.                                                             */
+float oracle_reduce(float theta)
+{
+    float turns = theta * reduction_constant();
+    float whole = rintf(turns);
+    return turns - whole;
+}
+
+/* Series (Sec. II polynomials): *s ~ sin(pi x / 2), *c ~ cos(pi x / 2) for
+ * the reduced angle x.                                                     */
+void oracle_quarter_series(float x, int arith, int method, float *s, float *c)
 {
     struct series_coeffs k = method_coeffs(method);
-    float q2 = q1 * q1;
-
-    float t = mul_add(q2, k.ss4, k.ss3, arith);
-    t = mul_add(q2, t, k.ss2, arith);
-    t = mul_add(q2, t, k.ss1, arith);
-    *s1 = q1 * t;
-
-    float u = mul_add(q2, k.cc3, k.cc2, arith);
-    u = mul_add(q2, u, k.cc1, arith);
-    *c1 = mul_add(q2, u, 1.0f, arith);
+    const float sin_coef[4] = {k.ss1, k.ss2, k.ss3, k.ss4};
+    const float cos_coef[4] = {1.0f, k.cc1, k.cc2, k.cc3};
+    float x2 = x * x;
+    *s = x * horner(x2, sin_coef, 4, arith);
+    *c = horner(x2, cos_coef, 4, arith);
 }
 
-/* Step 3, eq. (1): sin 2a = 2 sin a cos a, cos 2a = cos^2 a - sin^2 a.    */
+/* eq. (1): sin 2u = 2 sin u cos u, cos 2u = cos^2 u - sin^2 u.  The sine's
+ * product is rounded before it is doubled (doubling a rounded product is
+ * exact; rounding 2s * c instead would differ among subnormals).           */
 void oracle_double_angle(float s, float c, int arith, float *s_out, float *c_out)
 {
-    float cc = c * c;
-    *c_out = mul_sub_from(s, s, cc, arith);
-    float sc = s * c;
-    *s_out = 2.0f * sc;
+    float cos_sq = c * c;
+    *c_out = mul_sub_from(s, s, cos_sq, arith);
+    float sin_cos = s * c;
+    *s_out = 2.0f * sin_cos;
 }
 
-/* Step 4: magnitude factor from the pair after the first doubling.  If that
- * pair has squared magnitude 1 + e, the final pair has magnitude ~ 1 + e,
- * and the factor is ~ 1 - e.                                               */
-float oracle_magnitude_factor(float s2, float c2, int arith, int method)
+/* The rejected eq. (2): sin 2u = 2 sin u cos u, cos 2u = 1 - 2 sin^2 u
+ * (ablation only).                                                         */
+void oracle_double_angle_eq2(float s, float c, int arith, float *s_out, float *c_out)
+{
+    float twice_sin = 2.0f * s;
+    *c_out = mul_sub_from(twice_sin, s, 1.0f, arith);
+    float sin_cos = s * c;
+    *s_out = 2.0f * sin_cos;
+}
+
+/* Magnitude factor from a pair p whose squared magnitude 1 + e equals the
+ * final pair's magnitude: 1 - e = 2 - |p|^2 (method 1), 1 / |p|^2 (method 2). */
+float oracle_magnitude_factor(float s, float c, int arith, int method)
 {
     if (method == ORACLE_METHOD2) {
-        float cc = c2 * c2;
-        float d = mul_add(s2, s2, cc, arith);
-        return 1.0f / d;
+        float cos_sq = c * c;
+        float mag_sq = mul_add(s, s, cos_sq, arith);
+        return 1.0f / mag_sq;
     }
-    float inner = mul_sub_from(c2, c2, 2.0f, arith);
-    return mul_sub_from(s2, s2, inner, arith);
+    float two_less_cos_sq = mul_sub_from(c, c, 2.0f, arith);
+    return mul_sub_from(s, s, two_less_cos_sq, arith);
 }
 
-/* Steps 2-4 on an already reduced angle q1 in [-1/2, 1/2].                 */
-void oracle_pair_from_reduced(float q1, int arith, int method, float *s, float *c)
+/* Series, two doublings and the magnitude factor, on a reduced angle x in
+ * [-1/2, 1/2].  The factor is read from the pair after the first doubling,
+ * whose squared magnitude is the final magnitude.                          */
+void oracle_pair_from_reduced(float x, int arith, int method, float *s, float *c)
 {
-    float s1, c1, s2, c2, s3, c3;
-    oracle_quarter_series(q1, arith, method, &s1, &c1);
-    oracle_double_angle(s1, c1, arith, &s2, &c2);
-    float m = oracle_magnitude_factor(s2, c2, arith, method);
-    oracle_double_angle(s2, c2, arith, &s3, &c3);
-    *s = s3 * m;
-    *c = c3 * m;
+    float qs, qc, hs, hc, fs, fc;
+    oracle_quarter_series(x, arith, method, &qs, &qc); /* angle pi x / 2 */
+    oracle_double_angle(qs, qc, arith, &hs, &hc);      /* angle pi x     */
+    float m = oracle_magnitude_factor(hs, hc, arith, method);
+    oracle_double_angle(hs, hc, arith, &fs, &fc);      /* angle 2 pi x   */
+    *s = fs * m;
+    *c = fc * m;
 }
 
-/* Steps 1-4: the sine-cosine pair of the angle x (radians).               */
-void oracle_sincos_pair(float x, int arith, int method, float *s, float *c)
+/* The sine-cosine pair of the angle theta (radians).                       */
+void oracle_sincos_pair(float theta, int arith, int method, float *s, float *c)
 {
-    oracle_pair_from_reduced(oracle_reduce(x), arith, method, s, c);
+    oracle_pair_from_reduced(oracle_reduce(theta), arith, method, s, c);
 }
 
-/* Same pair without step 4 (the drifted magnitude the fix removes).        */
-void oracle_pair_unfixed(float q1, int arith, int method, float *s, float *c)
+/* The same pair without the magnitude factor (the drift it removes).       */
+void oracle_pair_unfixed(float x, int arith, int method, float *s, float *c)
 {
-    float s1, c1, s2, c2;
-    oracle_quarter_series(q1, arith, method, &s1, &c1);
-    oracle_double_angle(s1, c1, arith, &s2, &c2);
-    oracle_double_angle(s2, c2, arith, s, c);
+    float qs, qc, hs, hc;
+    oracle_quarter_series(x, arith, method, &qs, &qc);
+    oracle_double_angle(qs, qc, arith, &hs, &hc);
+    oracle_double_angle(hs, hc, arith, s, c);
 }
 
 /* ---------------------------------------------------------------------- */
 /* Ablations of Sec. II (analysis only; the method is oracle_pair_from_reduced).
- *   ORACLE_VARIANT_LISTING    the method: fix 2 - |p2|^2 taken after doubling 1
+ *   ORACLE_VARIANT_LISTING    the method: factor 2 - |p|^2 read after doubling 1
  *   ORACLE_VARIANT_NO_FIX     no magnitude correction
  *   ORACLE_VARIANT_TEXT_FIX   the text's form: (3 - s^2 - c^2)/2 on the final pair
  *   ORACLE_VARIANT_EQ2        both doublings with the rejected eq. (2),
- *                             cos 2a = 1 - 2 sin^2 a, then the listing's fix     */
+ *                             cos 2u = 1 - 2 sin^2 u, then the method's factor */
 #define ORACLE_VARIANT_LISTING 0
 #define ORACLE_VARIANT_NO_FIX 1
 #define ORACLE_VARIANT_TEXT_FIX 2
 #define ORACLE_VARIANT_EQ2 3
 
-static void double_angle_eq2(float s, float c, int arith, float *s_out, float *c_out)
+/* (3 - s^2 - c^2) / 2: one Newton step towards 1/|p| from |p|^2 = 1 + e. */
+static float text_factor(float s, float c, int arith)
 {
-    float two_s = 2.0f * s;
-    *c_out = mul_sub_from(two_s, s, 1.0f, arith); /* 1 - 2 s^2 */
-    float sc = s * c;
-    *s_out = 2.0f * sc;
+    float three_less_cos_sq = mul_sub_from(c, c, 3.0f, arith);
+    float h = mul_sub_from(s, s, three_less_cos_sq, arith);
+    return 0.5f * h;
 }
 
-void oracle_pair_variant(float q1, int arith, int method, int variant, float *s, float *c)
+void oracle_pair_variant(float x, int arith, int method, int variant, float *s, float *c)
 {
-    float s1, c1, s2, c2, s3, c3;
-    oracle_quarter_series(q1, arith, method, &s1, &c1);
+    float qs, qc, hs, hc, fs, fc;
+    oracle_quarter_series(x, arith, method, &qs, &qc);
     if (variant == ORACLE_VARIANT_EQ2) {
-        double_angle_eq2(s1, c1, arith, &s2, &c2);
-        float m = oracle_magnitude_factor(s2, c2, arith, method);
-        double_angle_eq2(s2, c2, arith, &s3, &c3);
-        *s = s3 * m;
-        *c = c3 * m;
+        oracle_double_angle_eq2(qs, qc, arith, &hs, &hc);
+        float m = oracle_magnitude_factor(hs, hc, arith, method);
+        oracle_double_angle_eq2(hs, hc, arith, &fs, &fc);
+        *s = fs * m;
+        *c = fc * m;
         return;
     }
-    oracle_double_angle(s1, c1, arith, &s2, &c2);
-    oracle_double_angle(s2, c2, arith, &s3, &c3);
+    oracle_double_angle(qs, qc, arith, &hs, &hc);
+    oracle_double_angle(hs, hc, arith, &fs, &fc);
     if (variant == ORACLE_VARIANT_NO_FIX) {
-        *s = s3;
-        *c = c3;
-    } else if (variant == ORACLE_VARIANT_TEXT_FIX) {
-        float h = mul_sub_from(s3, s3, mul_sub_from(c3, c3, 3.0f, arith), arith);
-        float m = 0.5f * h;
-        *s = s3 * m;
-        *c = c3 * m;
-    } else {
-        float m = oracle_magnitude_factor(s2, c2, arith, method);
-        *s = s3 * m;
-        *c = c3 * m;
+        *s = fs;
+        *c = fc;
+        return;
     }
+    float m = variant == ORACLE_VARIANT_TEXT_FIX ? text_factor(fs, fc, arith)
+                                                 : oracle_magnitude_factor(hs, hc, arith, method);
+    *s = fs * m;
+    *c = fc * m;
 }
 
 /* ---------------------------------------------------------------------- */
@@ -247,48 +292,35 @@ void oracle_pair_variant(float q1, int arith, int method, int variant, float *s,
  * error and squares the magnitude, so a series over a smaller angle (shorter,
  * for the same fit error) can be followed by more doublings, at the price of
  * a magnitude drift and first-pair rounding that grow with 2^n.  Here the
- * series approximate sin and cos of 2 pi q1 / 2^n (n = ndoub; n = 2 is the
- * method, whose quarter angle is pi q1 / 2):
- *   s1 = q1 (ss[0] + ss[1] q2 + ... + ss[ns-1] q2^(ns-1))
- *   c1 = 1 + q2 (cc[0] + cc[1] q2 + ... + cc[nc-1] q2^(nc-1))
- * by Horner in q2 as in step 2.  Then n doublings with eq. (1).  With fix,
- * the factor 2 - s^2 - c^2 is taken from the pair that precedes the last
- * doubling: that pair's squared magnitude is the final magnitude a^(2^n), as
- * the pair after doubling 1 is for n = 2 in Fig. 1.  For n = 0 the text's
- * (3 - s^2 - c^2) / 2 is applied to the series pair instead.  With n = 2,
- * the first method's coefficients and fix, this is step 2-4 exactly.       */
-void oracle_pair_general(float q1, int arith, int ndoub, const float *ss, int ns,
+ * series approximate sin and cos of 2 pi x / 2^n (n = ndoub; n = 2 is the
+ * method, whose quarter angle is pi x / 2):
+ *   s = x (ss[0] + ss[1] x2 + ... + ss[ns-1] x2^(ns-1))
+ *   c = 1 + x2 (cc[0] + cc[1] x2 + ... + cc[nc-1] x2^(nc-1))
+ * by Horner's rule in x2 as in the method.  Then n doublings with eq. (1).
+ * With fix, the factor 2 - |p|^2 is read from the pair that precedes the
+ * last doubling, whose squared magnitude is the final magnitude a^(2^n).
+ * With no doubling at all (n = 0) there is no earlier pair: the text's
+ * (3 - s^2 - c^2) / 2 is applied to the series pair itself.  With n = 2, the
+ * first method's coefficients and fix, this is the method exactly.        */
+void oracle_pair_general(float x, int arith, int ndoub, const float *ss, int ns,
                          const float *cc, int nc, int fix, float *s, float *c)
 {
-    float q2 = q1 * q1;
-    float t = ss[ns - 1];
-    for (int k = ns - 2; k >= 0; k--)
-        t = mul_add(q2, t, ss[k], arith);
-    float sv = q1 * t;
-    float u = cc[nc - 1];
-    for (int k = nc - 2; k >= 0; k--)
-        u = mul_add(q2, u, cc[k], arith);
-    float cv = mul_add(q2, u, 1.0f, arith);
+    float x2 = x * x;
+    float ps = x * horner(x2, ss, ns, arith);
+    float pc = mul_add(x2, horner(x2, cc, nc, arith), 1.0f, arith);
     float m = 1.0f;
-    if (ndoub == 0 && fix) {
-        float h = mul_sub_from(sv, sv, mul_sub_from(cv, cv, 3.0f, arith), arith);
-        m = 0.5f * h;
-    }
+    if (ndoub == 0 && fix)
+        m = text_factor(ps, pc, arith);
     for (int d = 0; d < ndoub; d++) {
         if (fix && d == ndoub - 1)
-            m = oracle_magnitude_factor(sv, cv, arith, ORACLE_METHOD1);
-        float s2, c2;
-        oracle_double_angle(sv, cv, arith, &s2, &c2);
-        sv = s2;
-        cv = c2;
+            m = oracle_magnitude_factor(ps, pc, arith, ORACLE_METHOD1);
+        float ds, dc;
+        oracle_double_angle(ps, pc, arith, &ds, &dc);
+        ps = ds;
+        pc = dc;
     }
-    if (fix) {
-        *s = sv * m;
-        *c = cv * m;
-    } else {
-        *s = sv;
-        *c = cv;
-    }
+    *s = fix ? ps * m : ps;
+    *c = fix ? pc * m : pc;
 }
 
 /* ---------------------------------------------------------------------- */
@@ -420,11 +452,11 @@ static void ablation_chunk(void *job, int64_t lo, int64_t hi)
 {
     struct ablation_job *j = (struct ablation_job *)job;
     for (int64_t i = lo; i < hi; i++) {
-        const float q1 = oracle_reduce(j->x[i]);
+        const float x = oracle_reduce(j->x[i]);
         if (j->variant >= 0)
-            oracle_pair_variant(q1, j->arith, j->method, j->variant, &j->s[i], &j->c[i]);
+            oracle_pair_variant(x, j->arith, j->method, j->variant, &j->s[i], &j->c[i]);
         else
-            oracle_pair_general(q1, j->arith, j->ndoub, j->ss, j->ns, j->cc, j->nc, j->fix,
+            oracle_pair_general(x, j->arith, j->ndoub, j->ss, j->ns, j->cc, j->nc, j->fix,
                                 &j->s[i], &j->c[i]);
     }
 }

@@ -192,3 +192,52 @@ def test_array_drivers_follow_the_scalar_ablations(orc):
     s, c = oracle.sincos_general(x[:300], 4, ss4, cc4, oracle.FUSED, fix=False)
     want = [oracle.pair_general(float(v), 4, ss4, cc4, oracle.FUSED, fix=False) for v in q]
     assert [(a, b) for a, b in zip(s, c)] == want
+
+
+# ---------------------------------------------------------------------------
+# Pins of the ablation paths themselves (tests/ablation_pins.py): the
+# rejected eq. (2) against the closed form of the stability analysis, the
+# text's factor and the n = 0 general form against (3 - |p|^2)/2 in double,
+# and every ablation against the exact-rational composition of its steps.
+
+import ablation_pins  # noqa: E402
+
+
+def test_eq2_doubling_matches_the_closed_form(orc):
+    """Pairs (a sin t, a cos t) with planted magnitudes 0.5 ... 2 go to
+    (a^2 sin 2t, a^2 cos 2t + (1 - a^2)) under eq. (2), to rounding."""
+    assert ablation_pins.eq2_closed_form(oracle.lib()) == []
+
+
+@pytest.mark.parametrize("arith", [oracle.FUSED, oracle.SPLIT])
+@pytest.mark.parametrize("method", [oracle.METHOD1, oracle.METHOD2])
+def test_eq2_variant_follows_its_model_with_an_upper_bound(orc, arith, method):
+    """The eq. (2) variant's angle is the closed form applied twice to the
+    series pair, within the rounding of two doublings; so its angle error is
+    bounded above by the model's error plus 1.3e-6.  With the second
+    method's series (magnitude far from 1) eq. (2) turns the angle by
+    2.4e-3: the leak of Sec. II, predicted by the model."""
+    bad, err_model, err_oracle = ablation_pins.eq2_model(oracle.lib(), arith, method)
+    assert bad == [], (bad, err_model, err_oracle)
+    if method == oracle.METHOD1:
+        assert err_oracle < 6.2e-7
+    else:
+        assert 2.3e-3 < err_oracle < 2.5e-3
+
+
+def test_text_factor_matches_its_closed_form(orc):
+    assert ablation_pins.text_factor_closed_form(oracle.lib()) == []
+
+
+def test_general_form_without_doublings(orc):
+    """n = 0: the series pair fixed with (3 - |p|^2)/2 has magnitude within
+    2e-7 of 1 and the series' own angle."""
+    from oracle import series_fit
+    assert ablation_pins.general_n0(oracle.lib(), *series_fit.fit_series(0, 6, 6)) == []
+
+
+def test_ablations_match_the_exact_rational_composition(orc):
+    from oracle import series_fit
+    series = {n: series_fit.fit_series(n, ns, nc) for n, ns, nc in ((0, 6, 6), (1, 5, 4),
+                                                                    (3, 3, 3))}
+    assert ablation_pins.exact_ablation_bits(oracle.lib(), series) == []

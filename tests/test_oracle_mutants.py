@@ -20,29 +20,37 @@ SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 
 
 MUTANTS = {
     "ss2_sign": ("k.ss2 = (float)-0.645963615;", "k.ss2 = (float)0.645963615;"),
-    "drop_ss4": ("float t = mul_add(q2, k.ss4, k.ss3, arith);", "float t = k.ss3;"),
-    "drop_cc3": ("float u = mul_add(q2, k.cc3, k.cc2, arith);", "float u = k.cc2;"),
-    "cc1_cc2_swapped": ("u = mul_add(q2, u, k.cc1, arith);\n    *c1 = mul_add(q2, u, 1.0f, arith);",
-                        "u = mul_add(q2, u, k.cc2, arith);\n    *c1 = mul_add(q2, u, 1.0f, arith);"),
+    "drop_ss4": ("const float sin_coef[4] = {k.ss1, k.ss2, k.ss3, k.ss4};",
+                 "const float sin_coef[4] = {k.ss1, k.ss2, k.ss3, 0.0f};"),
+    "drop_cc3": ("const float cos_coef[4] = {1.0f, k.cc1, k.cc2, k.cc3};",
+                 "const float cos_coef[4] = {1.0f, k.cc1, k.cc2, 0.0f};"),
+    "cc1_cc2_swapped": ("const float cos_coef[4] = {1.0f, k.cc1, k.cc2, k.cc3};",
+                        "const float cos_coef[4] = {1.0f, k.cc2, k.cc1, k.cc3};"),
     "ss3_digit_typo": ("k.ss3 = (float)0.0796819754;", "k.ss3 = (float)0.0769819754;"),
-    "doubling_plus": ("*c_out = mul_sub_from(s, s, cc, arith);", "*c_out = mul_add(s, s, cc, arith);"),
-    "doubling_no_two": ("*s_out = 2.0f * sc;", "*s_out = sc;"),
-    "rejected_doubling": ("*c_out = mul_sub_from(s, s, cc, arith);",
-                          "(void)cc; *c_out = mul_sub_from(2.0f * s, s, 1.0f, arith);"),
-    "one_doubling": ("oracle_double_angle(s2, c2, arith, &s3, &c3);", "s3 = s2; c3 = c2;"),
-    "no_fix": ("*s = s3 * m;\n    *c = c3 * m;", "(void)m;\n    *s = s3;\n    *c = c3;"),
-    "fix_sign": ("return mul_sub_from(s2, s2, inner, arith);", "return mul_add(s2, s2, inner, arith);"),
-    "ties_away": ("float r = rintf(x1);", "float r = roundf(x1);"),
-    "truncate": ("float r = rintf(x1);", "float r = truncf(x1);"),
-    "reduce_sign": ("return x1 - r;", "return r - x1;"),
+    "horner_order": ("for (int k = n - 2; k >= 0; k--)\n        p = mul_add(x2, p, coef[k], arith);",
+                     "for (int k = 0; k <= n - 2; k++)\n        p = mul_add(x2, p, coef[k], arith);"),
+    "doubling_plus": ("*c_out = mul_sub_from(s, s, cos_sq, arith);",
+                      "*c_out = mul_add(s, s, cos_sq, arith);"),
+    "doubling_no_two": ("*s_out = 2.0f * sin_cos;", "*s_out = sin_cos;"),
+    "rejected_doubling": ("*c_out = mul_sub_from(s, s, cos_sq, arith);",
+                          "(void)cos_sq; *c_out = mul_sub_from(2.0f * s, s, 1.0f, arith);"),
+    "one_doubling": ("oracle_double_angle(hs, hc, arith, &fs, &fc);      /* angle 2 pi x   */",
+                     "fs = hs; fc = hc;"),
+    "no_fix": ("*s = fs * m;\n    *c = fc * m;", "(void)m;\n    *s = fs;\n    *c = fc;"),
+    "fix_sign": ("return mul_sub_from(s, s, two_less_cos_sq, arith);",
+                 "return mul_add(s, s, two_less_cos_sq, arith);"),
+    "ties_away": ("float whole = rintf(turns);", "float whole = roundf(turns);"),
+    "truncate": ("float whole = rintf(turns);", "float whole = truncf(turns);"),
+    "reduce_sign": ("return turns - whole;", "return whole - turns;"),
     "pi_digits": ("(float)(1.0 / (2.0 * 3.1415926536))", "(float)(1.0 / (2.0 * 3.14159))"),
     "split_fuses": ("float p = a * b;\n    return p + c;", "return fmaf(a, b, c);"),
     "fused_splits": ("return fmaf(a, b, c);\n    float p = a * b;\n    return p + c;",
                      "{ float p = a * b; return p + c; }"),
-    "flush_subnormal": ("float x1 = x * reduction_constant();",
-                        "float x1 = x * reduction_constant();\n    if (fabsf(x1) < 1.17549435e-38f) x1 = 0.0f;"),
-    "fix_before_doubling": ("*s = s3 * m;\n    *c = c3 * m;",
-                            "oracle_double_angle(s2 * m, c2 * m, arith, s, c);"),
+    "flush_subnormal": ("float turns = theta * reduction_constant();",
+                        "float turns = theta * reduction_constant();\n"
+                        "    if (fabsf(turns) < 1.17549435e-38f) turns = 0.0f;"),
+    "fix_before_doubling": ("*s = fs * m;\n    *c = fc * m;",
+                            "oracle_double_angle(hs * m, hc * m, arith, s, c);"),
 }
 
 FLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-pthread"]
@@ -197,3 +205,70 @@ def test_huygens_mutant_fails_a_pin(tmp_path, name):
     old, new = HUYGENS_MUTANTS[name]
     assert old in src, "mutation site not found: " + name
     assert huygens_pins_fail(_build(tmp_path, name, src.replace(old, new, 1))), name
+
+
+# ---------------------------------------------------------------------------
+# The ablation paths of Sec. II: the rejected eq. (2) doubling, the text's
+# magnitude factor and the general form with n = 0 doublings.
+
+ABLATION_MUTANTS = {
+    "eq2_cos_for_sin": ("float twice_sin = 2.0f * s;\n    *c_out = mul_sub_from(twice_sin, s, 1.0f, arith);",
+                        "float twice_sin = 2.0f * c;\n    *c_out = mul_sub_from(twice_sin, c, 1.0f, arith);"),
+    "eq2_sign": ("*c_out = mul_sub_from(twice_sin, s, 1.0f, arith);",
+                 "*c_out = mul_add(twice_sin, s, 1.0f, arith);"),
+    "eq2_no_two": ("float twice_sin = 2.0f * s;", "float twice_sin = s;"),
+    "eq2_sine_no_two": ("*s_out = 2.0f * sin_cos;\n}\n\n/* Magnitude factor",
+                        "*s_out = sin_cos;\n}\n\n/* Magnitude factor"),
+    "eq2_second_doubling_eq1": ("oracle_double_angle_eq2(hs, hc, arith, &fs, &fc);",
+                                "oracle_double_angle(hs, hc, arith, &fs, &fc);"),
+    "eq2_factor_from_series": ("float m = oracle_magnitude_factor(hs, hc, arith, method);\n"
+                               "        oracle_double_angle_eq2",
+                               "float m = oracle_magnitude_factor(qs, qc, arith, method);\n"
+                               "        oracle_double_angle_eq2"),
+    "text_factor_unhalved": ("return 0.5f * h;", "return h;"),
+    "text_factor_two": ("float three_less_cos_sq = mul_sub_from(c, c, 3.0f, arith);",
+                        "float three_less_cos_sq = mul_sub_from(c, c, 2.0f, arith);"),
+    "text_factor_sign": ("float h = mul_sub_from(s, s, three_less_cos_sq, arith);",
+                         "float h = mul_add(s, s, three_less_cos_sq, arith);"),
+    "n0_no_fix": ("if (ndoub == 0 && fix)\n        m = text_factor(ps, pc, arith);",
+                  "if (ndoub == 0 && fix)\n        m = 1.0f;"),
+    "n0_listing_factor": ("if (ndoub == 0 && fix)\n        m = text_factor(ps, pc, arith);",
+                          "if (ndoub == 0 && fix)\n"
+                          "        m = oracle_magnitude_factor(ps, pc, arith, ORACLE_METHOD1);"),
+    "general_fix_from_series": ("if (fix && d == ndoub - 1)", "if (fix && d == 0)"),
+    "general_cos_no_one": ("float pc = mul_add(x2, horner(x2, cc, nc, arith), 1.0f, arith);",
+                           "float pc = x2 * horner(x2, cc, nc, arith);"),
+}
+
+
+@pytest.fixture(scope="module")
+def ablation_series():
+    from oracle import series_fit
+    return {n: series_fit.fit_series(n, ns, nc) for n, ns, nc in ((0, 6, 6), (1, 5, 4), (3, 3, 3),
+                                                                  (4, 3, 2))}
+
+
+def ablation_pins_fail(L, series):
+    import ablation_pins as ap
+    bad = ap.eq2_closed_form(L)
+    for arith in (0, 1):
+        for method in (0, 1):
+            bad += ap.eq2_model(L, arith, method, npts=1001)[0]
+    bad += ap.text_factor_closed_form(L)
+    bad += ap.general_n0(L, *series[0])
+    bad += ap.exact_ablation_bits(L, {n: series[n] for n in (0, 1, 3)})
+    bad += ap.general_fix_holds(L, {n: series[n] for n in (1, 3, 4)})
+    return bad
+
+
+def test_unmodified_oracle_passes_ablation_pins(tmp_path, ablation_series):
+    assert ablation_pins_fail(_build(tmp_path, "aclean", open(SRC).read()), ablation_series) == []
+
+
+@pytest.mark.parametrize("name", sorted(ABLATION_MUTANTS))
+def test_ablation_mutant_fails_a_pin(tmp_path, name, ablation_series):
+    src = open(SRC).read()
+    old, new = ABLATION_MUTANTS[name]
+    assert src.count(old) == 1, "mutation site not unique: " + name
+    bad = ablation_pins_fail(_build(tmp_path, name, src.replace(old, new)), ablation_series)
+    assert bad, "no pin caught mutant " + name
