@@ -370,9 +370,21 @@ typedef struct {
 
 SINCOS_API int sincos_server_create(const sincos_server_config_t *cfg, sincos_server_t **out);
 /* Queue a request of n >= 1 elements; *out_id receives its id.  Returns
- * SINCOS_EBUDGET if 12 n exceeds the whole budget.  Thread-safe.          */
+ * SINCOS_EBUDGET if 12 n exceeds the whole budget.  x must already hold its
+ * values for any stream (e.g. the producing stream was synchronized): the
+ * server's streams are not ordered after the caller's.  Thread-safe.      */
 SINCOS_API int sincos_server_submit(sincos_server_t *srv, const float *x, int64_t n, uint64_t tag,
                                     int64_t *out_id);
+/* The same, for an input produced by work enqueued on `stream` (a
+ * hipStream_t of the server's device; 0 = the null stream): an event is
+ * recorded on `stream` now, and the batch that carries the request waits for
+ * it on the device before reading x, so the caller need not synchronize.
+ * The calling thread's current device must be the server's (else EINVAL).
+ * x must stay allocated and unchanged until the request completes: a caller
+ * that frees it (or lets an allocator reuse it) before then gets undefined
+ * results.  A simulated server ignores `stream`.  Thread-safe.             */
+SINCOS_API int sincos_server_submit_on(sincos_server_t *srv, const float *x, int64_t n,
+                                       uint64_t tag, void *stream, int64_t *out_id);
 /* Up to `max` completions (waits up to timeout_ns for the first one).     */
 SINCOS_API int sincos_server_poll(sincos_server_t *srv, sincos_completion_t *out, int32_t max,
                                   int32_t *count, int64_t timeout_ns);

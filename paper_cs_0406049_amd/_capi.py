@@ -110,6 +110,8 @@ _SIGNATURES = {
                                    _P]),
     "sincos_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)]),
     "sincos_server_submit": (ctypes.c_int, [_P, _P, _I64, ctypes.c_uint64, ctypes.POINTER(_I64)]),
+    "sincos_server_submit_on": (ctypes.c_int, [_P, _P, _I64, ctypes.c_uint64, _P,
+                                               ctypes.POINTER(_I64)]),
     "sincos_server_poll": (ctypes.c_int, [_P, ctypes.POINTER(Completion), _I32,
                                           ctypes.POINTER(_I32), _I64]),
     "sincos_server_release": (ctypes.c_int, [_P, _I64]),

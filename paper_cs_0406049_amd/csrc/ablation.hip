@@ -1,5 +1,6 @@
 // ablation.hip -- the ablations of Sec. II on the GPU, for analysis and
-// measurement (the product's pair is pair_exact in sincos_core.hpp):
+// measurement (the product's pair is pair_exact in sincos_core.hpp, whose
+// steps these kernels reuse):
 //   * the method's alternatives: no magnitude fix; the text's fix
 //     (3 - s^2 - c^2)/2 applied to the final pair; both doublings with the
 //     rejected eq. (2), cos 2a = 1 - 2 sin^2 a;
@@ -22,21 +23,6 @@ namespace mi355 {
 
 namespace {
 
-__device__ __forceinline__ float reduce1(float x)
-{
-    const float x1 = x * kInvTwoPi;
-    return x1 - __builtin_rintf(x1);
-}
-
-// eq. (1): (s, c) <- (2 s c, c^2 - s^2)
-template <Arith A> __device__ __forceinline__ void double_eq1(float &s, float &c)
-{
-    const float c2 = mul_sub_from<A>(s, s, c * c);
-    const float s2 = 2.0f * (s * c);
-    s = s2;
-    c = c2;
-}
-
 // eq. (2): (s, c) <- (2 s c, 1 - 2 s^2)
 template <Arith A> __device__ __forceinline__ void double_eq2(float &s, float &c)
 {
@@ -44,15 +30,6 @@ template <Arith A> __device__ __forceinline__ void double_eq2(float &s, float &c
     const float s2 = 2.0f * (s * c);
     s = s2;
     c = c2;
-}
-
-// The factor after the first doubling: 2 - c^2 - s^2, or 1/(s^2 + c^2).
-template <Arith A, Method M> __device__ __forceinline__ float fix_factor(float s, float c)
-{
-    if constexpr (M == Method::Normalized)
-        return mul_sub_from<A>(s, s, mul_sub_from<A>(c, c, 2.0f));
-    else
-        return 1.0f / mul_add<A>(s, s, c * c);
 }
 
 // The text's factor (3 - c^2 - s^2) / 2.
@@ -64,36 +41,28 @@ template <Arith A> __device__ __forceinline__ float text_factor(float s, float c
 template <Arith A, Method M, int V>
 __device__ __forceinline__ void pair_variant(float x, float &s, float &c)
 {
-    using S = Series<M>;
-    const float q1 = reduce1(x);
-    const float q2 = q1 * q1;
-    float t = mul_add<A>(q2, S::ss4, S::ss3);
-    t = mul_add<A>(q2, t, S::ss2);
-    t = mul_add<A>(q2, t, S::ss1);
-    float sv = q1 * t;
-    float u = mul_add<A>(q2, S::cc3, S::cc2);
-    u = mul_add<A>(q2, u, S::cc1);
-    float cv = mul_add<A>(q2, u, 1.0f);
+    const Pair quarter = quarter_pair<A, M>(reduce_turns(x));
     if constexpr (V == SINCOS_VARIANT_EQ2) {
+        float sv = quarter.s, cv = quarter.c;
         double_eq2<A>(sv, cv);
-        const float m = fix_factor<A, M>(sv, cv);
+        const float m = norm_factor<A, M>({sv, cv});
         double_eq2<A>(sv, cv);
         s = sv * m;
         c = cv * m;
     } else {
-        double_eq1<A>(sv, cv);
-        const float m = fix_factor<A, M>(sv, cv);  // used by the listing variant only
-        double_eq1<A>(sv, cv);
+        const Pair half = double_angle<A>(quarter);
+        const float m = norm_factor<A, M>(half);  // used by the method's variant only
+        const Pair whole = double_angle<A>(half);
         if constexpr (V == SINCOS_VARIANT_NO_FIX) {
-            s = sv;
-            c = cv;
+            s = whole.s;
+            c = whole.c;
         } else if constexpr (V == SINCOS_VARIANT_TEXT_FIX) {
-            const float mt = text_factor<A>(sv, cv);
-            s = sv * mt;
-            c = cv * mt;
+            const float mt = text_factor<A>(whole.s, whole.c);
+            s = whole.s * mt;
+            c = whole.c * mt;
         } else {
-            s = sv * m;
-            c = cv * m;
+            s = whole.s * m;
+            c = whole.c * m;
         }
     }
 }
@@ -111,11 +80,11 @@ template <Arith A>
 __device__ __forceinline__ void pair_doublings4(const float (&x)[4], const DoublingArgs &g,
                                                 float (&s)[4], float (&c)[4])
 {
-    float q1[4], q2[4], t[4], u[4], m[4];
+    float xr[4], x2[4], t[4], u[4], m[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        q1[r] = reduce1(x[r]);
-        q2[r] = q1[r] * q1[r];
+        xr[r] = reduce_turns(x[r]);
+        x2[r] = xr[r] * xr[r];
         t[r] = g.ss[g.ns - 1];
         u[r] = g.cc[g.nc - 1];
         m[r] = 1.0f;
@@ -124,19 +93,19 @@ __device__ __forceinline__ void pair_doublings4(const float (&x)[4], const Doubl
         const float a = g.ss[k];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            t[r] = mul_add<A>(q2[r], t[r], a);
+            t[r] = mul_add<A>(x2[r], t[r], a);
     }
     for (int k = g.nc - 2; k >= 0; --k) {
         const float a = g.cc[k];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            u[r] = mul_add<A>(q2[r], u[r], a);
+            u[r] = mul_add<A>(x2[r], u[r], a);
     }
     float sv[4], cv[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        sv[r] = q1[r] * t[r];
-        cv[r] = mul_add<A>(q2[r], u[r], 1.0f);
+        sv[r] = xr[r] * t[r];
+        cv[r] = mul_add<A>(x2[r], u[r], 1.0f);
     }
     if (g.ndoub == 0 && g.fix) {
 #pragma unroll
@@ -147,11 +116,14 @@ __device__ __forceinline__ void pair_doublings4(const float (&x)[4], const Doubl
         if (g.fix && d == g.ndoub - 1) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                m[r] = fix_factor<A, Method::Normalized>(sv[r], cv[r]);
+                m[r] = norm_factor<A, Method::Normalized>({sv[r], cv[r]});
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            double_eq1<A>(sv[r], cv[r]);
+        for (int r = 0; r < 4; ++r) {
+            const Pair d2 = double_angle<A>({sv[r], cv[r]});
+            sv[r] = d2.s;
+            cv[r] = d2.c;
+        }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {

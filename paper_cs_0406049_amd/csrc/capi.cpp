@@ -104,7 +104,12 @@ LaunchShape resolve_ragged_shape(const LaunchShape &req, int64_t total_units,
     LaunchShape sh = req;
     // default: one workgroup per unit of work (measured faster than a
     // persistent grid); a requested grid is capped to the number of units
-    const int64_t cap = std::min<int64_t>(std::max<int64_t>(total_units, 1), int64_t(1) << 30);
+    // at most 2^30 workgroups, and grid * block below 2^32 (the dispatch
+    // packet counts work-items in 32 bits); each workgroup then takes a
+    // contiguous run of units
+    const int64_t max_grid = std::min<int64_t>(int64_t(1) << 30,
+                                               int64_t(UINT32_MAX) / std::max(sh.block, 1));
+    const int64_t cap = std::min<int64_t>(std::max<int64_t>(total_units, 1), max_grid);
     sh.grid = (int)(sh.grid <= 0 ? cap : std::min<int64_t>(sh.grid, cap));
     return sh;
 }
@@ -469,7 +474,7 @@ extern "C" int sincos_f32_interleaved(const float *x, float *out, int64_t n, int
         return set_error(SINCOS_EINVAL, "sincos_f32_interleaved: null pointer with n > 0");
     if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(out)) & 15)
         return set_error(SINCOS_EINVAL, "sincos_f32_interleaved: x and out must be 16-byte aligned");
-    if (n > (int64_t)INT32_MAX * 512)  // one 128-thread workgroup per 512 elements
+    if (n > (int64_t(1) << 36))  // 256 GiB of angles: beyond any device memory
         return set_error(SINCOS_EINVAL, "sincos_f32_interleaved: n too large");
     // out holds 2n floats (layout 1 rounds the last block up to 8 floats)
     const int64_t out_floats = layout == 0 ? 2 * n : 8 * ((n + 3) / 4);
@@ -518,7 +523,7 @@ extern "C" int sincos_pair_ceiling_f32(const float *x, float *out, int64_t n, in
         return set_error(SINCOS_EINVAL, "sincos_pair_ceiling_f32: n < 0 or reps < 0");
     if (n == 0)
         return SINCOS_OK;
-    if (n > (int64_t)INT32_MAX * 256)
+    if (n > (int64_t)(UINT32_MAX / 256) * 256)  // one 256-thread workgroup per 256 lanes
         return set_error(SINCOS_EINVAL, "sincos_pair_ceiling_f32: n too large");
     if (!x || !out || !aligned4(x) || !aligned4(out))
         return set_error(SINCOS_EINVAL, "sincos_pair_ceiling_f32: null or misaligned pointer");
@@ -928,7 +933,7 @@ extern "C" int sinusoid_f32_backward(const float *t, const float *g, int64_t N, 
     clear_error();
     if (N < 0)
         return set_error(SINCOS_EINVAL, "sinusoid_f32_backward: N < 0");
-    if (sinusoid_parts(N) > INT32_MAX)
+    if (sinusoid_parts(N) > (int64_t)(UINT32_MAX / 1024))  // 1024-thread workgroups
         return set_error(SINCOS_EINVAL, "sinusoid_f32_backward: N too large");
     int rc = check_params(A, w, phi, K, "sinusoid_f32_backward");
     if (rc != SINCOS_OK)
@@ -974,7 +979,7 @@ extern "C" int sinusoid_f32_fit_step(const float *t, const float *y_obs, int64_t
     const char *who = "sinusoid_f32_fit_step";
     if (N < 0)
         return set_error(SINCOS_EINVAL, std::string(who) + ": N < 0");
-    if (sinusoid_fit_parts(N) > INT32_MAX)
+    if (sinusoid_fit_parts(N) > (int64_t)(UINT32_MAX / 1024))  // 1024-thread workgroups
         return set_error(SINCOS_EINVAL, std::string(who) + ": N too large");
     int rc = check_params(A, w, phi, K, who);
     if (rc != SINCOS_OK)
@@ -1014,7 +1019,7 @@ extern "C" int huygens_f32(const float *xo, const float *yo, int64_t P, const fl
         return set_error(SINCOS_EINVAL, "huygens_f32: P < 0 or S < 0");
     if (P == 0)
         return SINCOS_OK;
-    if (P > (int64_t)INT32_MAX * 256)  // one 256-thread workgroup per 256 points
+    if (P > (int64_t(1) << 36))  // beyond any device memory
         return set_error(SINCOS_EINVAL, "huygens_f32: P too large");
     if (!xo || !yo || !re || !im || (S > 0 && !src))
         return set_error(SINCOS_EINVAL, "huygens_f32: null pointer");

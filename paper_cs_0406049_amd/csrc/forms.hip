@@ -30,30 +30,37 @@ __global__ void __launch_bounds__(64 * kIntWaves) k_sincos_interleaved(const f4 
     __shared__ f4 stage[kIntWaves][128];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int64_t i = (int64_t)blockIdx.x * (64 * kIntWaves) + threadIdx.x;
-    // first float4 of x for this wave
-    const int64_t wbase = (int64_t)blockIdx.x * (64 * kIntWaves) + wave * 64;
-    if (wbase >= n4)
-        return;  // whole wave past the end (wave-uniform)
-    f4 so = f4{0.f, 0.f, 0.f, 0.f}, co = so;
-    if (i < n4)
-        pair4<Arith::Fused, Method::Normalized>(__builtin_nontemporal_load(x + i), so, co);
-    if (LAYOUT == 0) {
-        stage[wave][2 * lane] = f4{co.x, so.x, co.y, so.y};
-        stage[wave][2 * lane + 1] = f4{co.z, so.z, co.w, so.w};
-    } else {
-        stage[wave][2 * lane] = so;
-        stage[wave][2 * lane + 1] = co;
+    // grid-stride over tiles of 64 * kIntWaves float4 of x
+    for (int64_t tile = blockIdx.x; tile * (64 * kIntWaves) < n4; tile += gridDim.x) {
+        const int64_t i = tile * (64 * kIntWaves) + threadIdx.x;
+        // first float4 of x for this wave
+        const int64_t wbase = tile * (64 * kIntWaves) + wave * 64;
+        if (wbase >= n4)
+            return;  // whole wave past the end (wave-uniform); later tiles are too
+        f4 so = f4{0.f, 0.f, 0.f, 0.f}, co = so;
+        if (i < n4)
+            pair4<Arith::Fused, Method::Normalized>(__builtin_nontemporal_load(x + i), so, co);
+        if (LAYOUT == 0) {
+            stage[wave][2 * lane] = f4{co.x, so.x, co.y, so.y};
+            stage[wave][2 * lane + 1] = f4{co.z, so.z, co.w, so.w};
+        } else {
+            stage[wave][2 * lane] = so;
+            stage[wave][2 * lane + 1] = co;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int64_t valid = min<int64_t>(64, n4 - wbase);  // float4 of x this wave covers
+        f4 *dst = out + 2 * wbase;
+        if (lane < 2 * valid)
+            __builtin_nontemporal_store(stage[wave][lane], dst + lane);
+        if (64 + lane < 2 * valid)
+            __builtin_nontemporal_store(stage[wave][64 + lane], dst + 64 + lane);
+        // the wave's reads of its stage rows finish before the next tile writes them
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int64_t valid = min<int64_t>(64, n4 - wbase);  // float4 of x this wave covers
-    f4 *dst = out + 2 * wbase;
-    if (lane < 2 * valid)
-        __builtin_nontemporal_store(stage[wave][lane], dst + lane);
-    if (64 + lane < 2 * valid)
-        __builtin_nontemporal_store(stage[wave][64 + lane], dst + 64 + lane);
 }
 
 // The last n % 4 elements of an interleaved output (complex layout: pair i at
@@ -571,36 +578,39 @@ __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *y
                                                  const f4 *__restrict__ src, int32_t S, float k,
                                                  float L, float L2, float *re, float *im)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const float px = i < P ? xo[i] : 0.f;
-    const float py = i < P ? yo[i] : 0.f;
-    float ar = 0.0f, ai = 0.0f;
-    const int32_t full = S / kHuyGroup * kHuyGroup;  // sources in whole groups
-    f4 cur[kHuyGroup];
-    if (full > 0) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i - threadIdx.x < P;
+         i += stride) {  // block-uniform loop condition
+        const float px = i < P ? xo[i] : 0.f;
+        const float py = i < P ? yo[i] : 0.f;
+        float ar = 0.0f, ai = 0.0f;
+        const int32_t full = S / kHuyGroup * kHuyGroup;  // sources in whole groups
+        f4 cur[kHuyGroup];
+        if (full > 0) {
 #pragma unroll
-        for (int u = 0; u < kHuyGroup; ++u)
-            cur[u] = src[u];
-    }
-    for (int32_t q = 0; q < full; q += kHuyGroup) {
-        // the next group; the last group reloads itself, so every index is < S
-        const int32_t nq = min(q + kHuyGroup, full - kHuyGroup);
-        f4 nxt[kHuyGroup];
+            for (int u = 0; u < kHuyGroup; ++u)
+                cur[u] = src[u];
+        }
+        for (int32_t q = 0; q < full; q += kHuyGroup) {
+            // the next group; the last group reloads itself, so every index is < S
+            const int32_t nq = min(q + kHuyGroup, full - kHuyGroup);
+            f4 nxt[kHuyGroup];
 #pragma unroll
-        for (int u = 0; u < kHuyGroup; ++u)
-            nxt[u] = src[nq + u];
+            for (int u = 0; u < kHuyGroup; ++u)
+                nxt[u] = src[nq + u];
 #pragma unroll
-        for (int u = 0; u < kHuyGroup; ++u)
-            huygens_term(px, py, cur[u], k, L, L2, ar, ai);
+            for (int u = 0; u < kHuyGroup; ++u)
+                huygens_term(px, py, cur[u], k, L, L2, ar, ai);
 #pragma unroll
-        for (int u = 0; u < kHuyGroup; ++u)
-            cur[u] = nxt[u];
-    }
-    for (int32_t q = full; q < S; ++q)
-        huygens_term(px, py, src[q], k, L, L2, ar, ai);
-    if (i < P) {
-        re[i] = ar;
-        im[i] = ai;
+            for (int u = 0; u < kHuyGroup; ++u)
+                cur[u] = nxt[u];
+        }
+        for (int32_t q = full; q < S; ++q)
+            huygens_term(px, py, src[q], k, L, L2, ar, ai);
+        if (i < P) {
+            re[i] = ar;
+            im[i] = ai;
+        }
     }
 }
 
@@ -699,7 +709,8 @@ hipError_t launch_sincos_interleaved(const float *x, float *out, int64_t n, int 
     const int64_t n4 = n / 4;
     if (n4 > 0) {
         const int per_block = 64 * kIntWaves;
-        const int64_t grid = (n4 + per_block - 1) / per_block;
+        // grid-stride past 2^20 workgroups: grid * block stays far below 2^32
+        const int64_t grid = std::min<int64_t>((n4 + per_block - 1) / per_block, int64_t(1) << 20);
         if (layout == 0)
             hipLaunchKernelGGL(k_sincos_interleaved<0>, dim3((unsigned)grid), dim3(per_block), 0,
                                st, reinterpret_cast<const f4 *>(x), reinterpret_cast<f4 *>(out), n4);
@@ -846,7 +857,9 @@ hipError_t launch_huygens(const float *xo, const float *yo, int64_t P, const flo
                           int32_t S, float k, float L, float *re, float *im, hipStream_t st)
 {
     const int64_t per_block = 256;
-    const int64_t grid = std::max<int64_t>(1, (P + per_block - 1) / per_block);
+    // grid-stride past 2^20 workgroups: grid * block stays far below 2^32
+    const int64_t grid = std::min<int64_t>(std::max<int64_t>(1, (P + per_block - 1) / per_block),
+                                           int64_t(1) << 20);
     const float L2 = L * L;
     hipLaunchKernelGGL(k_huygens, dim3((unsigned)grid), dim3(256), 0, st, xo, yo, P,
                        reinterpret_cast<const f4 *>(src), S, k, L, L2, re, im);

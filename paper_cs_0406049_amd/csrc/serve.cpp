@@ -51,6 +51,7 @@ struct Request {
     int32_t batch_requests = 0;
     int64_t t_submit = 0, t_admit = 0, t_launch = 0, t_complete = 0;
     bool released = false;
+    hipEvent_t ready = nullptr;  // recorded on the submitter's stream: x is ready after it
 };
 
 // Where batches run.  launch() starts a batch on a slot; query() reports
@@ -118,6 +119,9 @@ public:
         Slot &sl = slots_[slot];
         const LaunchShape shape = default_shape(mode_ == 1 ? kFormPlain : kFormRagged);
         int rc = SINCOS_OK;
+        for (Request *r : batch)  // inputs produced on the submitters' streams
+            if (r->ready && hipStreamWaitEvent(sl.stream, r->ready, 0) != hipSuccess)
+                return set_error(SINCOS_EHIP, "server: cannot wait for a request's input");
         if (mode_ == 1) {
             for (Request *r : batch) {
                 hipError_t e = launch_sincos(r->x, r->s, r->c, r->n, arith_, method_,
@@ -241,6 +245,7 @@ struct sincos_server {
     Arena arena;
     uint64_t budget_used = 0;
     sincos_server_stats_t stats{};
+    std::vector<hipEvent_t> event_pool;  // ready events not attached to a request
 
     // Owned by the scheduler thread alone.
     std::deque<Request *> pending;
@@ -269,6 +274,10 @@ struct sincos_server {
     // caller holds mu
     void complete(Request *r, int status, int64_t t)
     {
+        if (r->ready) {  // the batch that waited on it has finished (or never ran)
+            event_pool.push_back(r->ready);
+            r->ready = nullptr;
+        }
         r->status = status;
         r->t_complete = t;
         if (status == SINCOS_OK) {
@@ -511,25 +520,22 @@ extern "C" int sincos_server_create(const sincos_server_config_t *cfg, sincos_se
     return SINCOS_OK;
 }
 
-extern "C" int sincos_server_submit(sincos_server_t *srv, const float *x, int64_t n, uint64_t tag,
-                                    int64_t *out_id)
+static int submit_request(sincos_server_t *srv, const float *x, int64_t n, uint64_t tag,
+                          hipEvent_t ready, int64_t *out_id)
 {
-    clear_error();
-    if (!srv)
-        return set_error(SINCOS_EINVAL, "server_submit: null server");
-    if (n <= 0 || !x || (reinterpret_cast<uintptr_t>(x) & 3))
-        return set_error(SINCOS_EINVAL, "server_submit: need n >= 1 and a 4-byte aligned input");
-    if ((uint64_t)n * 12 > srv->budget)
-        return set_error(SINCOS_EBUDGET, "server_submit: request exceeds the whole budget");
     auto r = std::make_unique<Request>();
     r->x = x;
     r->n = n;
     r->tag = tag;
+    r->ready = ready;
     r->t_submit = now_ns();
     {
         std::lock_guard<std::mutex> lk(srv->mu);
-        if (srv->stop)
+        if (srv->stop) {
+            if (ready)
+                srv->event_pool.push_back(ready);
             return set_error(SINCOS_ECANCELED, "server_submit: server is stopping");
+        }
         r->id = srv->next_id++;
         if (out_id)
             *out_id = r->id;
@@ -539,6 +545,57 @@ extern "C" int sincos_server_submit(sincos_server_t *srv, const float *x, int64_
     }
     srv->cv_sched.notify_one();
     return SINCOS_OK;
+}
+
+static int check_submit(sincos_server_t *srv, const float *x, int64_t n, const char *who)
+{
+    if (!srv)
+        return set_error(SINCOS_EINVAL, std::string(who) + ": null server");
+    if (n <= 0 || !x || (reinterpret_cast<uintptr_t>(x) & 3))
+        return set_error(SINCOS_EINVAL,
+                         std::string(who) + ": need n >= 1 and a 4-byte aligned input");
+    if ((uint64_t)n * 12 > srv->budget)
+        return set_error(SINCOS_EBUDGET, std::string(who) + ": request exceeds the whole budget");
+    return SINCOS_OK;
+}
+
+extern "C" int sincos_server_submit(sincos_server_t *srv, const float *x, int64_t n, uint64_t tag,
+                                    int64_t *out_id)
+{
+    clear_error();
+    const int rc = check_submit(srv, x, n, "server_submit");
+    return rc != SINCOS_OK ? rc : submit_request(srv, x, n, tag, nullptr, out_id);
+}
+
+extern "C" int sincos_server_submit_on(sincos_server_t *srv, const float *x, int64_t n,
+                                       uint64_t tag, void *stream, int64_t *out_id)
+{
+    clear_error();
+    int rc = check_submit(srv, x, n, "server_submit_on");
+    if (rc != SINCOS_OK)
+        return rc;
+    if (srv->cfg.executor != 0)  // simulated: no device work to wait for
+        return submit_request(srv, x, n, tag, nullptr, out_id);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != srv->device)
+        return set_error(SINCOS_EINVAL, "server_submit_on: the calling thread's current device "
+                                        "is not the server's");
+    hipEvent_t ev = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (!srv->event_pool.empty()) {
+            ev = srv->event_pool.back();
+            srv->event_pool.pop_back();
+        }
+    }
+    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+        return set_error(SINCOS_EHIP, "server_submit_on: cannot create an event");
+    if (hipEventRecord(ev, (hipStream_t)stream) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->event_pool.push_back(ev);
+        return set_error(SINCOS_EHIP, "server_submit_on: cannot record on the stream");
+    }
+    return submit_request(srv, x, n, tag, ev, out_id);
 }
 
 static void fill_completion(const Request *r, bool auto_release, sincos_completion_t *o)
@@ -689,6 +746,18 @@ extern "C" int sincos_server_destroy(sincos_server_t *srv)
     if (srv->thread.joinable())
         srv->thread.join();
     srv->exec.reset();
+    if (srv->cfg.executor == 0) {
+        int prev = -1;
+        const bool restore = hipGetDevice(&prev) == hipSuccess && prev != srv->device;
+        (void)hipSetDevice(srv->device);
+        for (hipEvent_t ev : srv->event_pool)
+            (void)hipEventDestroy(ev);
+        for (auto &kv : srv->all)  // requests never completed keep theirs
+            if (kv.second->ready)
+                (void)hipEventDestroy(kv.second->ready);
+        if (restore)
+            (void)hipSetDevice(prev);
+    }
     delete srv;
     return SINCOS_OK;
 }

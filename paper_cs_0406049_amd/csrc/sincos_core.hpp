@@ -3,23 +3,28 @@
 //
 // One lane computes one pair with binary32 VALU operations only: no branch,
 // no table, no FP64, no packed FP32 (the library is built with packed FP32
-// disabled), IEEE subnormals kept (no flush).  Steps, as Sec. II of the paper
-// orders them:
-//   1. x1 = x * fl(1/(2 pi)); q1 = x1 - rint(x1)         (reduction mod 1)
-//   2. q2 = q1^2; s1 = q1 * P_s(q2); c1 = P_c(q2)        (quarter-angle series)
-//   3. (s2, c2) = (2 s1 c1, c1^2 - s1^2)                  (eq. (1) doubling)
-//   4. m = 2 - c2^2 - s2^2  (method 1)  or  1 / (s2^2 + c2^2)  (method 2)
-//   5. (s3, c3) = (2 s2 c2, c2^2 - s2^2)                  (second doubling)
-//   6. (s, c) = (s3 m, c3 m)                               (magnitude fix)
-// The magnitude factor is formed after the first doubling and applied to the
-// final pair, where the paper's sample implementation (Fig. 1) takes it.
-//
-// rint() is v_rndne_f32: round to nearest, ties to even, so q1 lies in
-// [-1/2, 1/2] and the subtraction is exact.  The paper writes every plain
-// product as a multiply-add with a +0 addend (AltiVec has no plain multiply);
-// here a product is a product, which changes no output (the reduced angle is
-// never -0).  2 * (s * c) keeps the product rounded first: the doubling of a
-// rounded product is exact, the rounding of 2s * c differs for subnormals.
+// disabled), IEEE subnormals kept (no flush).  The method of Sec. II:
+//   reduce   the angle times 1/(2 pi), less its nearest integer: the fraction
+//            of a turn x in [-1/2, 1/2] (round to nearest even, v_rndne_f32;
+//            the subtraction is exact);
+//   series   sine and cosine of the quarter angle pi x / 2: an odd and an
+//            even polynomial in x, Horner's rule in x^2;
+//   double   eq. (1) twice.  By the stability analysis of Sec. II a doubling
+//            squares the pair's magnitude and keeps its relative angle error;
+//   correct  after two doublings the magnitude is a^4, which is also the
+//            squared magnitude of the pair after the first doubling.  From
+//            that pair, |p|^2 = 1 + e, comes the factor 1/(1 + e): to first
+//            order 2 - |p|^2 (first method) or exactly 1 / |p|^2 (second).
+//            Formed there, it is computed beside the last doubling, whose
+//            result it rescales.
+// In FUSED arithmetic every product that feeds a sum is fused into it; in the
+// sums of two squares the cosine's square is the inner term and the sine's is
+// fused last, as in the paper's own implementation (Fig. 1), whose rounding
+// its printed accuracy figures reflect.  A plain product stays a product (the
+// vector unit the paper used has none and adds +0; the reduced angle is never
+// -0, so no output changes).  The sine of a doubling rounds s * c before
+// doubling it: doubling a rounded product is exact, rounding 2s * c is not
+// the same among subnormals.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -95,63 +100,85 @@ template <Arith A> __device__ __forceinline__ float mul_sub_from(float a, float 
     }
 }
 
-// Steps 1-6 with Fused or Split arithmetic.
-template <Arith A, Method M>
-__device__ __forceinline__ void pair_exact(float x, float &s, float &c)
+// A sine-cosine pair.
+struct Pair {
+    float s, c;
+};
+
+// Reduction: theta / (2 pi) less its nearest integer.
+__device__ __forceinline__ float reduce_turns(float theta)
+{
+    const float turns = theta * kInvTwoPi;
+    return turns - __builtin_rintf(turns);
+}
+
+// Horner's rule in x2: k0 + x2 (k1 + x2 (k2 + ...)).
+template <Arith A> __device__ __forceinline__ float horner(float, float top) { return top; }
+template <Arith A, typename... R>
+__device__ __forceinline__ float horner(float x2, float k0, R... rest)
+{
+    return mul_add<A>(x2, horner<A>(x2, rest...), k0);
+}
+
+// Series: (sin, cos) of the quarter angle pi x / 2.
+template <Arith A, Method M> __device__ __forceinline__ Pair quarter_pair(float x)
 {
     using S = Series<M>;
-    const float x1 = x * kInvTwoPi;
-    const float q1 = x1 - __builtin_rintf(x1);
-    const float q2 = q1 * q1;
+    const float x2 = x * x;
+    return {x * horner<A>(x2, S::ss1, S::ss2, S::ss3, S::ss4),
+            horner<A>(x2, 1.0f, S::cc1, S::cc2, S::cc3)};
+}
 
-    float t = mul_add<A>(q2, S::ss4, S::ss3);
-    t = mul_add<A>(q2, t, S::ss2);
-    t = mul_add<A>(q2, t, S::ss1);
-    const float s1 = q1 * t;
-    float u = mul_add<A>(q2, S::cc3, S::cc2);
-    u = mul_add<A>(q2, u, S::cc1);
-    const float c1 = mul_add<A>(q2, u, 1.0f);
+// eq. (1): (sin 2u, cos 2u) = (2 s c, c^2 - s^2).
+template <Arith A> __device__ __forceinline__ Pair double_angle(Pair p)
+{
+    return {2.0f * (p.s * p.c), mul_sub_from<A>(p.s, p.s, p.c * p.c)};
+}
 
-    const float c2 = mul_sub_from<A>(s1, s1, c1 * c1);
-    const float s2 = 2.0f * (s1 * c1);
+// Magnitude factor 1/(1 + e) from a pair with |p|^2 = 1 + e.
+template <Arith A, Method M> __device__ __forceinline__ float norm_factor(Pair p)
+{
+    if constexpr (M == Method::Normalized)
+        return mul_sub_from<A>(p.s, p.s, mul_sub_from<A>(p.c, p.c, 2.0f));  // 1 - e
+    else
+        return 1.0f / mul_add<A>(p.s, p.s, p.c * p.c);  // IEEE division, correctly rounded
+}
 
-    float m;
-    if constexpr (M == Method::Normalized) {
-        m = mul_sub_from<A>(s2, s2, mul_sub_from<A>(c2, c2, 2.0f));
-    } else {
-        m = 1.0f / mul_add<A>(s2, s2, c2 * c2);  // IEEE division (correctly rounded)
-    }
-
-    const float c3 = mul_sub_from<A>(s2, s2, c2 * c2);
-    const float s3 = 2.0f * (s2 * c2);
-    s = s3 * m;
-    c = c3 * m;
+// The method with FUSED or SPLIT arithmetic.
+template <Arith A, Method M>
+__device__ __forceinline__ void pair_exact(float theta, float &s, float &c)
+{
+    const Pair half = double_angle<A>(quarter_pair<A, M>(reduce_turns(theta)));
+    const float m = norm_factor<A, M>(half);  // |half|^2 is the final magnitude
+    const Pair whole = double_angle<A>(half);
+    s = whole.s * m;
+    c = whole.c * m;
 }
 
 // The Split expression tree with contraction allowed: the compiler may fuse
 // any product into the sum that consumes it.
 template <Method M>
-__device__ __forceinline__ void pair_contract(float x, float &s, float &c)
+__device__ __forceinline__ void pair_contract(float theta, float &s, float &c)
 {
 #pragma clang fp contract(fast)
     using S = Series<M>;
-    const float x1 = x * kInvTwoPi;
-    const float q1 = x1 - __builtin_rintf(x1);
-    const float q2 = q1 * q1;
-    const float s1 = q1 * (((q2 * S::ss4 + S::ss3) * q2 + S::ss2) * q2 + S::ss1);
-    const float c1 = ((q2 * S::cc3 + S::cc2) * q2 + S::cc1) * q2 + 1.0f;
-    const float c2 = c1 * c1 - s1 * s1;
-    const float s2 = 2.0f * (s1 * c1);
+    const float turns = theta * kInvTwoPi;
+    const float x = turns - __builtin_rintf(turns);
+    const float x2 = x * x;
+    const float qs = x * (((x2 * S::ss4 + S::ss3) * x2 + S::ss2) * x2 + S::ss1);
+    const float qc = ((x2 * S::cc3 + S::cc2) * x2 + S::cc1) * x2 + 1.0f;
+    const float hc = qc * qc - qs * qs;
+    const float hs = 2.0f * (qs * qc);
     float m;
     if constexpr (M == Method::Normalized) {
-        m = (2.0f - c2 * c2) - s2 * s2;
+        m = (2.0f - hc * hc) - hs * hs;
     } else {
-        m = 1.0f / (s2 * s2 + c2 * c2);
+        m = 1.0f / (hs * hs + hc * hc);
     }
-    const float c3 = c2 * c2 - s2 * s2;
-    const float s3 = 2.0f * (s2 * c2);
-    s = s3 * m;
-    c = c3 * m;
+    const float wc = hc * hc - hs * hs;
+    const float ws = 2.0f * (hs * hc);
+    s = ws * m;
+    c = wc * m;
 }
 
 template <Arith A, Method M>

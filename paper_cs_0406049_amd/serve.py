@@ -44,13 +44,28 @@ class Server:
         _capi._check(_capi.lib().sincos_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
         self.auto_release = bool(auto_release)
+        self._inputs = {}  # id -> input tensor, until its completion is polled
 
     def submit(self, x, n=None, tag: int = 0) -> int:
-        """Queue sin/cos of x (a device tensor or address); returns the id."""
+        """Queue sin/cos of x; returns the id.  A tensor may still be in the
+        making on the current stream: the request's batch waits on the device
+        for the work queued there so far (sincos_server_submit_on), and the
+        server keeps a reference to the tensor until its completion has been
+        polled, so its memory cannot be reused before the batch has read it.
+        An int address is taken as ready for every stream and is the
+        caller's to keep alive."""
         n = int(n if n is not None else x.numel())
-        ptr = x if isinstance(x, int) else _capi._ptr(x, n)
         rid = ctypes.c_int64()
-        _capi._check(_capi.lib().sincos_server_submit(self._h, ptr, n, int(tag), ctypes.byref(rid)))
+        if isinstance(x, int):
+            _capi._check(_capi.lib().sincos_server_submit(self._h, x, n, int(tag),
+                                                          ctypes.byref(rid)))
+            return rid.value
+        import torch
+        ptr = _capi._ptr(x, n)
+        stream = torch.cuda.current_stream(x.device).cuda_stream
+        _capi._check(_capi.lib().sincos_server_submit_on(self._h, ptr, n, int(tag), stream,
+                                                         ctypes.byref(rid)))
+        self._inputs[rid.value] = x
         return rid.value
 
     def poll(self, max_count: int = 256, timeout_s: float = 0.0):
@@ -58,7 +73,10 @@ class Server:
         k = ctypes.c_int32()
         _capi._check(_capi.lib().sincos_server_poll(self._h, buf, max_count, ctypes.byref(k),
                                                     int(timeout_s * 1e9)))
-        return [buf[i] for i in range(k.value)]
+        out = [buf[i] for i in range(k.value)]
+        for comp in out:
+            self._inputs.pop(comp.id, None)  # the batch has read it
+        return out
 
     def release(self, rid: int) -> None:
         _capi._check(_capi.lib().sincos_server_release(self._h, int(rid)))
@@ -99,8 +117,9 @@ class Server:
 
     def close(self) -> None:
         if self._h:
-            _capi.lib().sincos_server_destroy(self._h)
+            _capi.lib().sincos_server_destroy(self._h)  # waits for batches on the device
             self._h = None
+        self._inputs = {}
 
     def __enter__(self):
         return self

@@ -356,3 +356,25 @@ def test_fit_step_validation_and_workspace(L):
     assert call(gp=gp + 2) == _capi.EINVAL               # misaligned
     rc = f(t, yo, (1 << 31) * 2048 + 1, A, w, p, 8, loss, gA, gw, gp, ws, 1 << 40, None)
     assert rc == _capi.EINVAL and "too large" in _capi.last_error()
+
+
+def test_size_limits_keep_grids_below_the_dispatch_limit(L):
+    """The dispatch packet counts work-items in 32 bits: entry points with one
+    workgroup per fixed slice reject sizes whose grid * block would reach
+    2^32; grid-stride kernels take sizes up to 2^36 (beyond device memory)."""
+    rc = L.sincos_f32_interleaved(BASE, BASE + (1 << 44), (1 << 36) + 4, 0, None)
+    assert rc == _capi.EINVAL and "too large" in _capi.last_error()
+    src = BASE + (1 << 20)
+    rc = L.huygens_f32(BASE, BASE + 65536, (1 << 36) + 1, src, 4, 1.0, 100.0,
+                       BASE + 2 * 65536, BASE + 3 * 65536, None)
+    assert rc == _capi.EINVAL and "too large" in _capi.last_error()
+    rc = L.sincos_pair_ceiling_f32(BASE, BASE + (1 << 44), (0xFFFFFFFF // 256) * 256 + 1, 1, None)
+    assert rc == _capi.EINVAL and "too large" in _capi.last_error()
+    n_over = (0xFFFFFFFF // 1024) * 2048 + 1        # one 1024-thread workgroup too many
+    rc = L.sinusoid_f32_backward(BASE, BASE, n_over, BASE, BASE, BASE, 4, BASE, BASE, BASE, BASE,
+                                 1 << 40, None)
+    assert rc == _capi.EINVAL and "too large" in _capi.last_error()
+    t, yo, A, w, p = BASE, BASE + 65536, BASE + 2 * 65536, BASE + 3 * 65536, BASE + 4 * 65536
+    loss, gA, gw, gp, ws = (BASE + k * 65536 for k in range(5, 10))
+    rc = L.sinusoid_f32_fit_step(t, yo, n_over, A, w, p, 8, loss, gA, gw, gp, ws, 1 << 40, None)
+    assert rc == _capi.EINVAL and "too large" in _capi.last_error()

@@ -170,3 +170,44 @@ def test_served_workload_full_sampled(torch_dev):
     assert_bit_exact(np.concatenate(cs), co, "served full workload cos", x)
     log("served full workload: %d requests, %d batches, inflight peak %d, %d sampled outputs" % (
         st["completed"], st["batches"], st["inflight_peak"], x.size))
+
+
+def test_submit_waits_for_the_producing_stream_and_keeps_the_input(torch_dev):
+    """Inputs still being written on the current stream (host-to-device copies
+    queued behind a few milliseconds of matrix products) are submitted and
+    dropped at once.  The batches wait for the copies on the device, and the
+    server holds each tensor until its completion is polled, so the allocator
+    cannot hand its memory to the zero-filled tensors made right after: every
+    result is the oracle's bits."""
+    torch = torch_dev
+    from paper_cs_0406049_amd import serve
+    rng = np.random.default_rng(21)
+    sizes = [1000, 65536 + 3, 1 << 20]
+    hosts = [rng.uniform(-1e3, 1e3, n).astype(np.float32) for n in sizes]
+    pinned = [torch.from_numpy(h).pin_memory() for h in hosts]
+    a = torch.randn(4096, 4096, device="cuda")
+    b = torch.randn(4096, 4096, device="cuda") / 64.0
+    with serve.Server(max_inflight=2) as srv:
+        for j, h in enumerate(hosts):
+            x = torch.full((h.size,), float("nan"), device="cuda")
+            torch.cuda.synchronize()
+            for _ in range(4):
+                a = torch.mm(a, b)          # keeps the current stream busy
+            x.copy_(pinned[j], non_blocking=True)
+            srv.submit(x, tag=j)
+            del x
+            junk = torch.zeros(h.size, device="cuda")
+            del junk
+        comps = []
+        while len(comps) < len(sizes):
+            comps += srv.poll(16, 5.0)
+        assert not srv._inputs
+        for c in comps:
+            j = int(c.tag)
+            s, co = serve.Server.outputs(c)
+            so, cw = oracle.sincos(hosts[j], 0, 0)
+            assert_bit_exact(s.cpu().numpy(), so, "served sin %d" % j)
+            assert_bit_exact(co.cpu().numpy(), cw, "served cos %d" % j)
+            srv.release(c.id)
+    torch.cuda.synchronize()
+    log("submit_on: %d fresh inputs served bit-exact" % len(sizes))

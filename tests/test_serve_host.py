@@ -212,3 +212,20 @@ def test_replay_rejects_mismatched_tables():
     with sim(auto_release=True) as s:
         with pytest.raises(ValueError):
             s.replay([FAKE] * 3, np.full(4, 100, np.int64), np.zeros(4, np.int64))
+
+
+def test_submit_on_with_the_simulated_executor():
+    """submit_on takes the same arguments as submit plus a stream; a simulated
+    server has no device work to wait for and ignores the stream."""
+    import ctypes
+    with sim(budget_bytes=1 << 20) as s:
+        rid = ctypes.c_int64()
+        assert _capi.lib().sincos_server_submit_on(s._h, FAKE, 1000, 7, None,
+                                                   ctypes.byref(rid)) == _capi.OK
+        for bad_x, bad_n in ((0, 10), (FAKE + 2, 10), (FAKE, 0)):
+            assert _capi.lib().sincos_server_submit_on(s._h, bad_x, bad_n, 0, None,
+                                                       ctypes.byref(rid)) == _capi.EINVAL
+        assert _capi.lib().sincos_server_submit_on(s._h, FAKE, 1 << 20, 0, None,
+                                                   ctypes.byref(rid)) == _capi.EBUDGET
+        got = drain(s, 1)
+        assert len(got) == 1 and got[0].tag == 7 and got[0].status == _capi.OK
