@@ -243,6 +243,26 @@ SINCOS_API int sinusoid_f32_fit_step(const float *t, const float *y_obs, int64_t
                                      float *gA, float *gw, float *gphi, void *workspace,
                                      int64_t workspace_bytes, void *stream);
 
+/* sinusoid_f32_fit_step without a workspace argument, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, checks,
+ * results and bits as sinusoid_f32_fit_step; the partials go to a static
+ * device array of SINCOS_FIT_SCRATCH_BYTES that the library holds on each
+ * GPU it runs on until the process ends (its address is looked up on the
+ * first call per device, with that device current).  Nothing is allocated:
+ * no hipMalloc, hipFree or allocating library call.  EINVAL when
+ * sinusoid_f32_fit_step_workspace_bytes(N, K) exceeds
+ * SINCOS_FIT_SCRATCH_BYTES (at K <= 64: N above 22,253,568 samples).
+ * Every call writes all the scratch it reads before reading it, so nothing
+ * needs clearing; but all calls on one GPU share the one array, so calls
+ * that overlap in time on that GPU (other streams, other threads) race and
+ * may return wrong results: serialize them.                               */
+#define SINCOS_FIT_SCRATCH_BYTES (8 << 20)
+SINCOS_API int sinusoid_f32_fit_step_noalloc(const float *t, const float *y_obs, int64_t N,
+                                             const float *A, const float *w, const float *phi,
+                                             int32_t K, float *loss, float *gA, float *gw,
+                                             float *gphi, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Huygens' principle point-source sum (the application named in Sec. IV):
  * the complex field at P screen points (xo_i, yo_i, L) from S point sources

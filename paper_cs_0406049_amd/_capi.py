@@ -99,6 +99,8 @@ _SIGNATURES = {
     "sinusoid_f32_fit_step_workspace_bytes": (_I64, [_I64, _I32]),
     "sinusoid_f32_fit_step": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _P, _P, _P, _P, _P,
                                              _I64, _P]),
+    "sinusoid_f32_fit_step_noalloc": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _P, _P, _P,
+                                                     _P, _P]),
     "sincos_copy_ceiling_f32": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(Launch), _P]),
     "sincos_f32_interleaved": (ctypes.c_int, [_P, _P, _I64, _I32, _P]),
     "sincos_pair_ceiling_f32": (ctypes.c_int, [_P, _P, _I64, _I32, _P]),
@@ -402,6 +404,23 @@ def sinusoid_f32_fit_step(t, y_obs, A, w, phi, loss, gA, gw, gphi, workspace,
                                        _ptr(phi, K), K, _ptr(loss, 1), _ptr(gA, K), _ptr(gw, K),
                                        _ptr(gphi, K), _raw_ptr(workspace, int(workspace_bytes)),
                                        int(workspace_bytes), _stream(stream)))
+
+
+# Bytes of the library's static scratch used by sinusoid_f32_fit_step_noalloc
+# (SINCOS_FIT_SCRATCH_BYTES in sincos.h).
+FIT_SCRATCH_BYTES = 8 << 20
+
+
+def sinusoid_f32_fit_step_noalloc(t, y_obs, A, w, phi, loss, gA, gw, gphi, N=None, K=None,
+                                  stream=None) -> None:
+    """sinusoid_f32_fit_step with its partials in the library's static scratch
+    (no device allocation); calls on one GPU must not overlap in time."""
+    N = _numel(t, N)
+    K = _numel(A, K)
+    _check(lib().sinusoid_f32_fit_step_noalloc(_ptr(t, N), _ptr(y_obs, N), N, _ptr(A, K),
+                                               _ptr(w, K), _ptr(phi, K), K, _ptr(loss, 1),
+                                               _ptr(gA, K), _ptr(gw, K), _ptr(gphi, K),
+                                               _stream(stream)))
 
 
 def huygens_f32(xo, yo, src, k, L, re, im, P=None, S=None, stream=None) -> None:

@@ -970,13 +970,12 @@ extern "C" int64_t sinusoid_f32_fit_step_workspace_bytes(int64_t N, int32_t K)
     return sinusoid_fit_parts(N) * (3 * sinusoid_kgroups(K) * 64 + 1) * (int64_t)sizeof(float);
 }
 
-extern "C" int sinusoid_f32_fit_step(const float *t, const float *y_obs, int64_t N, const float *A,
-                                     const float *w, const float *phi, int32_t K, float *loss,
-                                     float *gA, float *gw, float *gphi, void *workspace,
-                                     int64_t workspace_bytes, void *stream)
+// Checks shared by the two fit-step entry points (everything but the
+// partials' buffer).
+static int check_fit_step(const float *t, const float *y_obs, int64_t N, const float *A,
+                          const float *w, const float *phi, int32_t K, const float *loss,
+                          const float *gA, const float *gw, const float *gphi, const char *who)
 {
-    clear_error();
-    const char *who = "sinusoid_f32_fit_step";
     if (N < 0)
         return set_error(SINCOS_EINVAL, std::string(who) + ": N < 0");
     if (sinusoid_fit_parts(N) > (int64_t)(UINT32_MAX / 1024))  // 1024-thread workgroups
@@ -988,7 +987,22 @@ extern "C" int sinusoid_f32_fit_step(const float *t, const float *y_obs, int64_t
         return set_error(SINCOS_EINVAL, std::string(who) + ": null loss or gradient output");
     if (N > 0 && (!t || !y_obs))
         return set_error(SINCOS_EINVAL, std::string(who) + ": null t or y_obs with N > 0");
-    if (!all_aligned4({t, y_obs, A, w, phi, loss, gA, gw, gphi, workspace}))
+    if (!all_aligned4({t, y_obs, A, w, phi, loss, gA, gw, gphi}))
+        return set_error(SINCOS_EINVAL, std::string(who) + ": pointers must be 4-byte aligned");
+    return SINCOS_OK;
+}
+
+extern "C" int sinusoid_f32_fit_step(const float *t, const float *y_obs, int64_t N, const float *A,
+                                     const float *w, const float *phi, int32_t K, float *loss,
+                                     float *gA, float *gw, float *gphi, void *workspace,
+                                     int64_t workspace_bytes, void *stream)
+{
+    clear_error();
+    const char *who = "sinusoid_f32_fit_step";
+    int rc = check_fit_step(t, y_obs, N, A, w, phi, K, loss, gA, gw, gphi, who);
+    if (rc != SINCOS_OK)
+        return rc;
+    if (!aligned4(workspace))
         return set_error(SINCOS_EINVAL, std::string(who) + ": pointers must be 4-byte aligned");
     const int64_t need = sinusoid_f32_fit_step_workspace_bytes(N, K);
     if (N > 0 && (!workspace || workspace_bytes < need))
@@ -1009,6 +1023,42 @@ extern "C" int sinusoid_f32_fit_step(const float *t, const float *y_obs, int64_t
     hipError_t e = launch_sinusoid_fit(t, y_obs, N, A, w, phi, K, loss, gA, gw, gphi, part,
                                        loss_part, (hipStream_t)stream);
     return e == hipSuccess ? SINCOS_OK : hip_error(e, "sinusoid_f32_fit_step: kernel launch");
+}
+
+extern "C" int sinusoid_f32_fit_step_noalloc(const float *t, const float *y_obs, int64_t N,
+                                             const float *A, const float *w, const float *phi,
+                                             int32_t K, float *loss, float *gA, float *gw,
+                                             float *gphi, void *stream)
+{
+    clear_error();
+    const char *who = "sinusoid_f32_fit_step_noalloc";
+    int rc = check_fit_step(t, y_obs, N, A, w, phi, K, loss, gA, gw, gphi, who);
+    if (rc != SINCOS_OK)
+        return rc;
+    const int64_t need = sinusoid_f32_fit_step_workspace_bytes(N, K);
+    if (need > kFitScratchBytes)
+        return set_error(SINCOS_EINVAL, std::string(who) + ": needs " + std::to_string(need) +
+                                            " bytes of partials, more than its " +
+                                            std::to_string(kFitScratchBytes) +
+                                            "-byte scratch; use sinusoid_f32_fit_step");
+    if ((rc = check_disjoint({{loss, 1, "loss"}, {gA, K, "gA"}, {gw, K, "gw"}, {gphi, K, "gphi"}},
+                             {{t, N, "t"}, {y_obs, N, "y_obs"}, {A, K, "A"}, {w, K, "w"},
+                              {phi, K, "phi"}},
+                             who)) != SINCOS_OK)
+        return rc;
+    const DeviceInfo *dev;
+    if ((rc = current_device(&dev)) != SINCOS_OK)
+        return rc;
+    float *part = nullptr;
+    hipError_t e = fit_scratch(dev->device, &part);
+    if (e != hipSuccess)
+        return hip_error(e, "sinusoid_f32_fit_step_noalloc: scratch address");
+    const int64_t parts = sinusoid_fit_parts(N);
+    float *loss_part = part + 3 * sinusoid_kgroups(K) * 64 * parts;
+    e = launch_sinusoid_fit(t, y_obs, N, A, w, phi, K, loss, gA, gw, gphi, part, loss_part,
+                            (hipStream_t)stream);
+    return e == hipSuccess ? SINCOS_OK
+                           : hip_error(e, "sinusoid_f32_fit_step_noalloc: kernel launch");
 }
 
 extern "C" int huygens_f32(const float *xo, const float *yo, int64_t P, const float *src,

@@ -5,6 +5,7 @@
 #include "stream.hpp"
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 namespace mi355 {
@@ -910,6 +911,30 @@ hipError_t launch_sinusoid_fit(const float *t, const float *y_obs, int64_t N, co
     hipLaunchKernelGGL(k_fit_reduce, dim3((unsigned)Kpad, 4), dim3(256), 0, st, partial, loss_part,
                        nparts, Kpad, K, A, gA, gw, gphi, loss);
     return hipGetLastError();
+}
+
+// Library-owned partials of the allocation-free fit step: one copy per GPU,
+// held until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol); it uses the
+// device address that fit_scratch() looks up once per device.
+static __device__ __align__(256) float scratch[kFitScratchBytes / sizeof(float)];
+
+hipError_t fit_scratch(int device, float **out)
+{
+    static std::mutex mu;
+    static float *addr[kMaxScratchDevices] = {};
+    if (device < 0 || device >= kMaxScratchDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        addr[device] = static_cast<float *>(p);
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_pair_ceiling(const float *x, float *out, int64_t n, int32_t reps,

@@ -105,6 +105,12 @@ hipError_t launch_sinusoid_fit(const float *t, const float *y_obs, int64_t N, co
                                const float *w, const float *phi, int32_t K, float *loss,
                                float *gA, float *gw, float *gphi, float *partial,
                                float *loss_part, hipStream_t stream);
+// The allocation-free fit step's partials live in a static device array of
+// kFitScratchBytes per GPU; fit_scratch() returns its device address on
+// `device` (which must be current), looked up on the first call per device.
+constexpr int64_t kFitScratchBytes = int64_t(8) << 20;
+constexpr int kMaxScratchDevices = 64;
+hipError_t fit_scratch(int device, float **out);
 hipError_t launch_sinusoid_backward(const float *t, const float *g, int64_t N, const float *A,
                                     const float *w, const float *phi, int32_t K, float *gA,
                                     float *gw, float *gphi, float *partial, hipStream_t stream);
