@@ -40,7 +40,13 @@ PMC_FILE = os.path.join(ROOT, "profiles", "plain_sincos_268M_pmc.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_cs_0406049_amd", "csrc", f)
                   for f in ("sincos_core.hpp", "stream.hpp", "plain.hip")]
 LAUNCH_SHAPE_SOURCE = os.path.join(ROOT, "paper_cs_0406049_amd", "csrc", "internal.hpp")
-CEILING_SHAPES = ((64, 1, 0), (256, 1, 0), (512, 1, 0))
+# (block, unroll, grid, lds): lds -1 reserves no LDS, otherwise the bytes each
+# workgroup reserves (which caps the workgroups resident per CU)
+CEILING_SHAPES = ((64, 1, 0, -1), (64, 1, 0, 7168), (64, 1, 0, 8192), (256, 1, 0, -1))
+# memory-traffic probes: (name, probe, shapes tried; the best is reported)
+READ_SHAPES = ((1024, 1, 0, -1), (256, 1, 0, -1))
+WRITE_SHAPES = ((64, 1, 0, -1), (64, 1, 0, 14336), (64, 1, 0, 16384), (256, 1, 0, -1))
+WRITE1_SHAPES = ((256, 1, 0, -1), (64, 1, 0, 16384))
 
 
 def log(msg):
@@ -164,13 +170,26 @@ def bench_ragged(torch, reps, plain_gbs):
         segs.append((x, torch.empty_like(x), torch.empty_like(x)))
     del xs_h
     elems = int(lens.sum())
-    shape = autotune.tune_ragged(segs, lens, cache_path=None, reps=3)
+    shape, table = autotune.tune_ragged_table(segs, lens, reps=3)
+
+    def best_where(pred):
+        for ms, sh in table:
+            if pred(sh):
+                return {"launch": dict(zip(("block", "unroll", "grid", "lds"), sh)),
+                        "kernel_ms": round(ms, 4)}
+        return None
+    persistent = best_where(lambda sh: sh[2] != autotune.COVER)
+    uncapped = best_where(lambda sh: sh[2] == autotune.COVER and sh[3] == -1)
     plan = _capi.RaggedPlan(segs, lens, launch=shape)
     # steady state: a graph launch costs ~15 us more than the bare kernel
     # when launches are back to back, more for the first few
     k_ms, _ = time_launches(torch, plan.launch, max(20, reps), 3)
     g_ms, _ = time_launches(torch, plan.graph_launch, max(20, reps), 3)
-    one_ms, _ = time_launches(torch, lambda: _capi.sincos_f32_ragged(segs, lens), reps, 2)
+    one_ms, _ = time_launches(torch, lambda: _capi.sincos_f32_ragged(segs, lens, launch=shape),
+                              reps, 2)
+    seg_table = _capi.SegTable(segs, lens)
+    tab_ms, _ = time_launches(torch, lambda: _capi.sincos_f32_ragged(seg_table, launch=shape),
+                              max(20, reps), 3)
 
     def per_array():
         for x, s_, c_ in segs:
@@ -180,12 +199,101 @@ def bench_ragged(torch, reps, plain_gbs):
     plan.destroy()
     return {"workload": "4096 arrays, lengths log-uniform in [100, 1e6] (seed 2), %d elements, "
                         "angles U[-100 pi, 100 pi)" % elems,
-            "autotuned_launch": {"block": shape[0], "unroll": shape[1], "grid": shape[2]},
+            "autotuned_launch": dict(zip(("block", "unroll", "grid", "lds"), shape)),
+            "candidates_timed": len(table),
+            "best_persistent": persistent, "best_one_per_unit_uncapped": uncapped,
             "graph_ms": round(g_ms, 4), "kernel_ms": round(k_ms, 4),
-            "oneshot_staged_ms": round(one_ms, 4), "per_array_plain_ms": round(pa_ms, 4),
+            "oneshot_staged_ms": round(one_ms, 4),
+            "oneshot_segtable_ms": round(tab_ms, 4),
+            "oneshot_segtable_vs_graph": round(tab_ms / g_ms, 3),
+            "per_array_plain_ms": round(pa_ms, 4),
             "gelem_s": round(elems / (g_ms * 1e-3) / 1e9, 2), "GBps": round(gbs, 1),
             "per_byte_vs_plain": round(gbs / plain_gbs, 4),
             "speedup_vs_per_array": round(pa_ms / g_ms, 2)}
+
+
+def memory_ceilings(torch, _capi, x, s, c, n, steps, warmup):
+    """What the HBM allows, measured with the library's memory probes (the
+    plain kernel's loads and stores with no arithmetic): the 1-read /
+    2-write copy in its launch shape (best of a few LDS reservations), the
+    same traffic in other schedules, a read-only stream, two and one write
+    streams, and the serial bound a perfect alternation of the best read and
+    write streams would reach (time = 4n / read rate + 8n / write rate).
+    Returns (best 1-read / 2-write GB/s in the plain kernel's schedule,
+    references)."""
+    P = _capi
+
+    def rate(probe, shape, policy=-1):
+        ms, _ = time_launches(torch, lambda: P.sincos_stream_probe_f32(
+            probe, x, s, c, n, launch=shape, policy=policy), steps, warmup)
+        return P.PROBE_BYTES[probe] * n / (ms * 1e-3) / 1e9
+
+    def best(probe, shapes):
+        got = [(rate(probe, sh), sh) for sh in shapes]
+        gbs, sh = max(got)
+        log("%s: %s" % (P.PROBE_NAMES[probe], ", ".join("%s %.0f" % (b, a) for a, b in got)))
+        return round(gbs, 1), dict(zip(("block", "unroll", "grid", "lds"), sh))
+
+    ceiling, ceiling_shape = best(P.PROBE_COPY, CEILING_SHAPES)
+    read, read_shape = best(P.PROBE_READ, READ_SHAPES)
+    write, write_shape = best(P.PROBE_WRITE, WRITE_SHAPES)
+    write1, write1_shape = best(P.PROBE_WRITE1, WRITE1_SHAPES)
+    schedules = {}
+    for name, probe, shape in (("copy_read_ahead_2", P.PROBE_COPY_BATCH, (64, 2, 0, -1)),
+                               ("copy_wave_per_stream", P.PROBE_COPY_SPLIT, (64, 1, 0, -1)),
+                               ("copy_wave_per_stream_lds", P.PROBE_COPY_LDS, (64, 1, 0, -1)),
+                               ("copy_xcd_contiguous", P.PROBE_COPY_XCD, (64, 1, 0, -1)),
+                               ("copy_persistent_8192", P.PROBE_COPY, (64, 1, 8192, -1)),
+                               ("copy_nt_sc1_stores", P.PROBE_COPY, (64, 1, 0, -1))):
+        schedules[name] = round(rate(probe, shape, 18 if name == "copy_nt_sc1_stores" else -1), 1)
+    log("1-read / 2-write schedules: %s" % schedules)
+    serial = 12.0 / (4.0 / read + 8.0 / write)
+    # references from the runtime and torch: a device-to-device copy
+    # (1 read : 1 write) and a fill (writes only), same array size
+    cp_ms, _ = time_launches(torch, lambda: s.copy_(x), steps, warmup)
+    fill_ms, _ = time_launches(torch, lambda: s.fill_(0.5), steps, warmup)
+    refs = {"copy_1r2w_best_shape": ceiling_shape,
+            "read_only_GBps": read, "read_only_shape": read_shape,
+            "write_only_2streams_GBps": write, "write_only_2streams_shape": write_shape,
+            "write_only_1stream_GBps": write1, "write_only_1stream_shape": write1_shape,
+            "serial_bound_1r2w_GBps": round(serial, 1),
+            "serial_bound_frac_of_peak": round(serial / HBM_PEAK_GBPS, 4),
+            "copy_1r2w_frac_of_serial_bound": round(ceiling / serial, 4),
+            "other_1r2w_schedules_GBps": schedules,
+            "torch_copy_1r1w_GBps": round(8 * n / (cp_ms * 1e-3) / 1e9, 1),
+            "torch_fill_write_only_GBps": round(4 * n / (fill_ms * 1e-3) / 1e9, 1)}
+    log("references: %s" % refs)
+    return ceiling, refs
+
+
+# the kernels of a counter pass, in dispatch order: (label, call)
+COUNTER_PASS = (
+    ("plain, no LDS reservation", lambda P, x, s, c, n: P.sincos_f32_ex(x, s, c, n, launch=(64, 1, 0, -1))),
+    ("plain, default (7168 B)", lambda P, x, s, c, n: P.sincos_f32_ex(x, s, c, n)),
+    ("read probe, 1024 threads", lambda P, x, s, c, n: P.sincos_stream_probe_f32(
+        P.PROBE_READ, x, s, None, n, launch=(1024, 1, 0, -1))),
+    ("write probe, no reservation", lambda P, x, s, c, n: P.sincos_stream_probe_f32(
+        P.PROBE_WRITE, None, s, c, n, launch=(64, 1, 0, -1))),
+    ("write probe, 16384 B", lambda P, x, s, c, n: P.sincos_stream_probe_f32(
+        P.PROBE_WRITE, None, s, c, n, launch=(64, 1, 0, 16384))),
+    ("copy probe, no reservation", lambda P, x, s, c, n: P.sincos_stream_probe_f32(
+        P.PROBE_COPY, x, s, c, n, launch=(64, 1, 0, -1))),
+    ("copy probe, 8192 B", lambda P, x, s, c, n: P.sincos_stream_probe_f32(
+        P.PROBE_COPY, x, s, c, n, launch=(64, 1, 0, 8192))),
+)
+
+
+def counter_pass(torch, _capi, n):
+    """Each kernel of COUNTER_PASS three times, in order (uniform angles)."""
+    x = torch.rand(n, device="cuda") * 100 - 50
+    s = torch.empty_like(x)
+    c = torch.empty_like(x)
+    for _ in range(3):
+        for _label, call in COUNTER_PASS:
+            call(_capi, x, s, c, n)
+    torch.cuda.synchronize()
+    print("counter pass done: %s" % "; ".join(label for label, _ in COUNTER_PASS), flush=True)
+    return 0
 
 
 def bench_variants(torch, reps, x, s, c):
@@ -492,8 +600,13 @@ def main(argv=None):
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--unroll", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--lds", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ceiling", action="store_true")
+    ap.add_argument("--counter-pass", action="store_true",
+                    help="only run the plain kernel (with and without its LDS reservation) and "
+                         "the read, write and copy probes three times each over the roofline "
+                         "workload's size, for rocprofv3 counter runs, then exit")
     ap.add_argument("--forms",
                     default="variants,ablations,ragged,interleaved,adjoint,sinusoid,huygens,serve",
                     help="comma list of forms to measure after the plain kernel ('' = none)")
@@ -519,6 +632,8 @@ def main(argv=None):
     log("device %s, %d CUs, %s" % (props.name, props.multi_processor_count, _capi.version()))
 
     n = args.n
+    if args.counter_pass:
+        return counter_pass(torch, _capi, n)
     log("generating %d angles" % n)
     if n == 1 << 28:
         x_host = workloads.plain_roofline(n)
@@ -532,8 +647,8 @@ def main(argv=None):
     c = torch.empty_like(x)
     arith = 0 if args.arith == "fused" else 1
     launch = None
-    if args.block or args.unroll or args.grid:
-        launch = (args.block, args.unroll, args.grid)
+    if args.block or args.unroll or args.grid or args.lds:
+        launch = (args.block, args.unroll, args.grid, args.lds)
     torch.cuda.synchronize()
 
     def step():
@@ -549,22 +664,7 @@ def main(argv=None):
     ceiling = None
     references = None
     if not args.no_ceiling:
-        # the same 1-read / 2-write float4 stream with no arithmetic, best of a
-        # few launch shapes
-        for shape in CEILING_SHAPES:
-            def copy_step():
-                _capi.sincos_copy_ceiling_f32(x, s, c, n, shape)
-            cev, _ = time_launches(torch, copy_step, args.steps, args.warmup)
-            gbs = BYTES_PER_ELEM * n / (cev * 1e-3) / 1e9
-            log("copy ceiling (1 read : 2 writes) %s: %.4f ms, %.0f GB/s" % (shape, cev, gbs))
-            ceiling = gbs if ceiling is None else max(ceiling, gbs)
-        # references from the runtime and torch: a device-to-device copy
-        # (1 read : 1 write) and a fill (writes only), same array size
-        cp_ms, _ = time_launches(torch, lambda: s.copy_(x), args.steps, args.warmup)
-        fill_ms, _ = time_launches(torch, lambda: s.fill_(0.5), args.steps, args.warmup)
-        references = {"torch_copy_1r1w_GBps": round(8 * n / (cp_ms * 1e-3) / 1e9, 1),
-                      "torch_fill_write_only_GBps": round(4 * n / (fill_ms * 1e-3) / 1e9, 1)}
-        log("references: %s" % references)
+        ceiling, references = memory_ceilings(torch, _capi, x, s, c, n, args.steps, args.warmup)
         step()  # leave the sine-cosine outputs in s, c
         torch.cuda.synchronize()
 
@@ -588,7 +688,8 @@ def main(argv=None):
                    "launch": {"block": args.block or default_plain["block"],
                               "unroll": args.unroll or default_plain["unroll"],
                               "grid": args.grid or default_plain["grid"] or
-                              "one workgroup per tile"},
+                              "one workgroup per tile",
+                              "lds_reserved_bytes": max(0, args.lds or default_plain["lds"])},
                    "device": props.name, "cus": props.multi_processor_count},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),

@@ -91,12 +91,19 @@ typedef enum {
  * unroll: float4 per thread per loop trip (1, 2, 4 or 8); built-in 1.
  * grid:   workgroups; built-in 0 = one per tile, covering the array once
  *         (grid-stride beyond 2^20 workgroups); for the ragged form one per
- *         unit of work, and a smaller grid makes the launch persistent.     */
+ *         unit of work, and a smaller grid makes the launch persistent.
+ * lds:    bytes of LDS each workgroup reserves at launch (up to 65536),
+ *         which caps how many workgroups a CU holds at once (a CU has
+ *         160 KiB); -1 = reserve none.  Built-in: 7168 for the plain form
+ *         (at most 22 resident 64-thread workgroups per CU, which keeps
+ *         fewer DRAM rows open at once: measured 1-2 % faster on MI355X),
+ *         none for the ragged form.  Used by the plain and ragged forms and
+ *         the memory probes; other forms ignore it.                         */
 typedef struct {
     int32_t block;
     int32_t unroll;
     int32_t grid;
-    int32_t reserved;
+    int32_t lds;
 } sincos_launch_t;
 
 /* ---------------------------------------------------------------------- */
@@ -286,6 +293,52 @@ SINCOS_API int huygens_f32(const float *xo, const float *yo, int64_t P, const fl
  * ceiling for the plain kernel.                                           */
 SINCOS_API int sincos_copy_ceiling_f32(const float *x, float *s, float *c, int64_t n,
                             const sincos_launch_t *launch, void *stream);
+
+/* Measurement helper: memory-traffic probes for the plain form's roofline.
+ * Each uses the plain kernel's buffer instructions with no arithmetic, over
+ * n elements (n >= 0, a multiple of 4; arrays 16-byte aligned, pairwise
+ * disjoint):
+ *   SINCOS_PROBE_READ        reads x (4 B per element); writes at most
+ *                            s[0], and only for inputs whose bits fold to a
+ *                            fixed unlikely word (the store keeps the loads).
+ *   SINCOS_PROBE_WRITE       writes s and c (8 B per element); x unused.
+ *   SINCOS_PROBE_WRITE1      writes s only (4 B per element); x, c unused.
+ *   SINCOS_PROBE_COPY        s = c = x in the plain kernel's schedule: one
+ *                            tile of block * unroll float4 per workgroup,
+ *                            s and c stored row by row (with the default
+ *                            policy, what sincos_copy_ceiling_f32 does).
+ *   SINCOS_PROBE_COPY_BATCH  s = c = x; a workgroup loads all `unroll` rows
+ *                            of its tile, then stores every row of s, then
+ *                            every row of c.
+ *   SINCOS_PROBE_COPY_SPLIT  s = c = x; two-wave workgroups (block 128) over
+ *                            64-float4 tiles: both waves load the tile, wave
+ *                            0 stores s and wave 1 stores c.
+ *   SINCOS_PROBE_COPY_LDS    s = c = x; two-wave workgroups over 128-float4
+ *                            tiles read once into LDS: wave 0 stores the
+ *                            tile to s, wave 1 to c.
+ *   SINCOS_PROBE_COPY_XCD    s = c = x in the plain schedule with unroll 1,
+ *                            the tiles dealt so that each of the 8 XCDs
+ *                            sweeps a contiguous eighth of the array.
+ * policy: -1 = the plain kernel's (loads non-temporal, stores sc1); for
+ * READ, WRITE, WRITE1 and COPY also the cache-policy bits of the stores (of
+ * the loads for READ): 0, 1 (sc0), 2 (nt), 16 (sc1), 17 (sc0|sc1) or 18
+ * (nt|sc1).  launch: as for sincos_f32_ex (NULL = the plain form's
+ * default, including its LDS reservation); the split and LDS probes
+ * always use 128 threads.  EINVAL for an
+ * unknown probe or policy or bad sizes, EOVERLAP for overlapping arrays.  */
+enum {
+    SINCOS_PROBE_READ = 0,
+    SINCOS_PROBE_WRITE = 1,
+    SINCOS_PROBE_WRITE1 = 2,
+    SINCOS_PROBE_COPY = 3,
+    SINCOS_PROBE_COPY_BATCH = 4,
+    SINCOS_PROBE_COPY_SPLIT = 5,
+    SINCOS_PROBE_COPY_LDS = 6,
+    SINCOS_PROBE_COPY_XCD = 7
+};
+SINCOS_API int sincos_stream_probe_f32(int32_t probe, int32_t policy, const float *x, float *s,
+                                       float *c, int64_t n, const sincos_launch_t *launch,
+                                       void *stream);
 
 /* Measurement helper: the VALU ceiling of the pair's instruction mix.  Lane i
  * runs 8 independent chains theta_r = x[i] + r (r = 0..7), adding 1 per step,

@@ -1,13 +1,13 @@
 """Launch-shape autotuner for the ragged form.
 
-For a ragged batch it times one plan per candidate (block, unroll, grid) with
+For a ragged batch it times one plan per candidate (block, unroll, grid, lds) with
 HIP events (the kernel only, each candidate replayed a few times after a
 warm-up), keeps the fastest, and caches the choice in a JSON file keyed by
 device architecture, CU count and a bucket of the batch's size (segment count
 and total elements, each rounded to a power of two), so a later batch of a
 similar size reuses it without timing.
 
-    shape = autotune.tune_ragged(segs, lens)        # (block, unroll, grid)
+    shape = autotune.tune_ragged(segs, lens)        # (block, unroll, grid, lds)
     plan = _capi.RaggedPlan(segs, lens, launch=shape)
 
 or, with install_default=True, the choice becomes the library's process-wide default
@@ -30,6 +30,12 @@ UNROLLS = (1, 2, 4)
 # 0 = one workgroup per unit of work (no persistence)
 WAVES_PER_CU = (8, 16, 32, 64, 128, 0)
 COVER = 1 << 30  # a grid this large is capped to the number of units
+# For the one-workgroup-per-unit grid: caps on resident waves per CU, applied
+# by reserving LDS in each workgroup (0 = no cap).  Fewer tiles in flight
+# keep fewer DRAM rows open; too few starve the reads.
+WAVE_CAPS = (0, 24, 16)
+LDS_PER_CU = 160 * 1024
+MAX_LDS = 65536
 
 _lock = threading.Lock()
 
@@ -61,12 +67,30 @@ def save_cache(cache: dict, path: str = DEFAULT_CACHE) -> None:
     os.replace(tmp, path)
 
 
+def lds_for_cap(block: int, cap: int):
+    """LDS bytes per workgroup that hold a CU to about `cap` resident waves
+    (-1: reserve none; None: not expressible for this block size)."""
+    if cap == 0:
+        return -1
+    wgs = cap // (block // 64)
+    if wgs < 1:
+        return None
+    lds = (LDS_PER_CU // wgs) // 256 * 256
+    return lds if lds <= MAX_LDS else None
+
+
 def candidates(cus: int):
+    """(block, unroll, grid, lds) launch shapes to time; lds -1 = none."""
     for block in BLOCKS:
         for unroll in UNROLLS:
             for wpc in WAVES_PER_CU:
-                grid = COVER if wpc == 0 else max(1, cus * wpc * 64 // block)
-                yield (block, unroll, grid)
+                if wpc:
+                    yield (block, unroll, max(1, cus * wpc * 64 // block), -1)
+                    continue
+                for cap in WAVE_CAPS:
+                    lds = lds_for_cap(block, cap)
+                    if lds is not None:
+                        yield (block, unroll, COVER, lds)
 
 
 def time_plan(torch, plan, reps: int = 5) -> float:
@@ -85,12 +109,16 @@ def time_plan(torch, plan, reps: int = 5) -> float:
 
 
 def install(form: str, shape) -> None:
-    """Make shape = (block, unroll, grid) the library's default launch shape
-    for form ("plain" or "ragged"), keeping the other form's default."""
+    """Make shape = (block, unroll, grid[, lds]) the library's default launch
+    shape for form ("plain" or "ragged"), keeping the other form's default
+    (lds -1, no reservation, is installed as 0)."""
     if form not in ("plain", "ragged"):
         raise ValueError("form must be 'plain' or 'ragged'")
     cur = _capi.get_tuning()
-    cur[form] = dict(zip(("block", "unroll", "grid"), (int(v) for v in shape)))
+    sh = dict(zip(("block", "unroll", "grid", "lds"), (int(v) for v in shape)))
+    sh.setdefault("lds", 0)
+    sh["lds"] = max(sh["lds"], 0)
+    cur[form] = sh
     _capi.set_tuning(cur)
 
 
@@ -98,14 +126,22 @@ def tune_ragged(segs, lens=None, arith: int = _capi.ARITH_FUSED,
                 method: int = _capi.METHOD_NORMALIZED, cache_path: str | None = DEFAULT_CACHE,
                 force: bool = False, reps: int = 5, verbose: bool = False,
                 install_default: bool = False):
-    """Best (block, unroll, grid) for this batch (from the cache if present).
+    """Best (block, unroll, grid, lds) for this batch (from the cache if present).
     The arrays' contents are overwritten with valid outputs while timing.
     With install_default, the choice also becomes the library's default for
     ragged calls (grid capped there to each call's units)."""
-    best = _tune_ragged(segs, lens, arith, method, cache_path, force, reps, verbose)
+    best, _ = _tune_ragged(segs, lens, arith, method, cache_path, force, reps, verbose)
     if install_default:
         install("ragged", best)
     return best
+
+
+def tune_ragged_table(segs, lens=None, arith: int = _capi.ARITH_FUSED,
+                      method: int = _capi.METHOD_NORMALIZED, reps: int = 5,
+                      verbose: bool = False):
+    """Time every candidate (no cache) and return (best, [(ms, shape), ...])
+    with the timings sorted fastest first."""
+    return _tune_ragged(segs, lens, arith, method, None, True, reps, verbose)
 
 
 def _tune_ragged(segs, lens, arith, method, cache_path, force, reps, verbose):
@@ -119,7 +155,7 @@ def _tune_ragged(segs, lens, arith, method, cache_path, force, reps, verbose):
     with _lock:
         cache = load_cache(cache_path) if cache_path else {}
         if not force and key in cache:
-            return tuple(cache[key]["shape"])
+            return tuple(cache[key]["shape"]), []
     results = []
     for shape in candidates(cus):
         plan = _capi.RaggedPlan(segs, lens, arith, method, launch=shape)
@@ -136,4 +172,4 @@ def _tune_ragged(segs, lens, arith, method, cache_path, force, reps, verbose):
             cache[key] = {"shape": list(best), "ms": best_ms, "elements": int(sum(lens)),
                           "segments": len(lens), "tried": len(results)}
             save_cache(cache, cache_path)
-    return best
+    return best, results

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmi355_sincos.so")
 
-SOURCES = ["plain.hip", "forms.hip", "ablation.hip", "capi.cpp", "serve.cpp", "tuning.cpp"]
+SOURCES = ["plain.hip", "forms.hip", "ablation.hip", "probes.hip", "capi.cpp", "serve.cpp", "tuning.cpp"]
 HEADERS = ["internal.hpp", "sincos_core.hpp", "stream.hpp", "serve.hpp"]
 
 # -ffp-contract=off: the SPLIT arithmetic must not be fused (FUSED uses

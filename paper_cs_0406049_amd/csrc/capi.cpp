@@ -90,6 +90,8 @@ static int check_shape(const sincos_launch_t *req, int form, LaunchShape *out)
             sh.unroll = req->unroll;
         if (req->grid != 0)
             sh.grid = req->grid;
+        if (req->lds != 0)
+            sh.lds = req->lds < 0 ? 0 : req->lds;
     }
     const int rc = validate_shape(sh, "launch");
     if (rc == SINCOS_OK)
@@ -513,6 +515,50 @@ extern "C" int sincos_copy_ceiling_f32(const float *x, float *s, float *c, int64
     hipError_t e = launch_copy_ceiling(x, s, c, n, resolve_plain_shape(sh, n, *dev),
                                        (hipStream_t)stream);
     return e == hipSuccess ? SINCOS_OK : hip_error(e, "sincos_copy_ceiling_f32: kernel launch");
+}
+
+extern "C" int sincos_stream_probe_f32(int32_t probe, int32_t policy, const float *x, float *s,
+                                       float *c, int64_t n, const sincos_launch_t *launch,
+                                       void *stream)
+{
+    clear_error();
+    const char *who = "sincos_stream_probe_f32";
+    if (probe < 0 || probe >= kProbeCount)
+        return set_error(SINCOS_EINVAL, std::string(who) + ": unknown probe " +
+                                            std::to_string(probe));
+    if (!probe_policy_ok(policy) || (policy != -1 && !probe_takes_policy(probe)))
+        return set_error(SINCOS_EINVAL, std::string(who) + ": policy " + std::to_string(policy) +
+                                            " not available for this probe");
+    if (n < 0 || n % 4 != 0)
+        return set_error(SINCOS_EINVAL, std::string(who) + ": n must be >= 0 and a multiple of 4");
+    const bool reads = probe != kProbeWrite && probe != kProbeWrite1;
+    const bool writes_c = probe != kProbeRead && probe != kProbeWrite1;
+    if ((reads && !x) || !s || (writes_c && !c))
+        return set_error(SINCOS_EINVAL, std::string(who) + ": null array");
+    const uintptr_t bits = reinterpret_cast<uintptr_t>(reads ? x : nullptr) |
+                           reinterpret_cast<uintptr_t>(s) |
+                           reinterpret_cast<uintptr_t>(writes_c ? c : nullptr);
+    if ((bits & 15) != 0)
+        return set_error(SINCOS_EINVAL, std::string(who) + ": arrays must be 16-byte aligned");
+    // outputs: s (one float for the read probe) and c; input: x
+    const int64_t ns = probe == kProbeRead ? 1 : n;
+    int rc = check_disjoint({{s, ns, "s"}, {writes_c ? c : nullptr, n, "c"}},
+                            {{reads ? x : nullptr, n, "x"}}, who);
+    if (rc != SINCOS_OK)
+        return rc;
+    LaunchShape sh;
+    if ((rc = check_shape(launch, kFormPlain, &sh)) != SINCOS_OK)
+        return rc;
+    if (probe == kProbeCopyXcd && (n / 4 + sh.block - 1) / sh.block + 8 > (int64_t(1) << 24))
+        return set_error(SINCOS_EINVAL, std::string(who) + ": n too large for the XCD schedule");
+    if (n == 0)
+        return SINCOS_OK;
+    const DeviceInfo *dev;
+    if ((rc = current_device(&dev)) != SINCOS_OK)
+        return rc;
+    hipError_t e = launch_stream_probe(probe, policy, x, s, c, n,
+                                       resolve_plain_shape(sh, n, *dev), (hipStream_t)stream);
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "sincos_stream_probe_f32: kernel launch");
 }
 
 extern "C" int sincos_pair_ceiling_f32(const float *x, float *out, int64_t n, int32_t reps,

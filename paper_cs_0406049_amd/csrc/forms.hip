@@ -669,10 +669,10 @@ hipError_t launch_ragged_am(const Tab &tab, int32_t count, int64_t total_units,
     do {                                                                                          \
         if constexpr (std::is_same<Tab, RaggedInline>::value)                                     \
             hipLaunchKernelGGL((k_ragged_inline<A, M, UU>), dim3((unsigned)grid), dim3(sh.block),  \
-                               0, st, tab, count, total_units, per);                              \
+                               (unsigned)sh.lds, st, tab, count, total_units, per);               \
         else                                                                                      \
-            hipLaunchKernelGGL((k_ragged<A, M, UU>), dim3((unsigned)grid), dim3(sh.block), 0, st, \
-                               tab.desc, tab.ubeg, count, total_units, per);                      \
+            hipLaunchKernelGGL((k_ragged<A, M, UU>), dim3((unsigned)grid), dim3(sh.block),         \
+                               (unsigned)sh.lds, st, tab.desc, tab.ubeg, count, total_units, per); \
     } while (0)
     switch (sh.unroll) {
     case 1: MI355_RAGGED(1); break;

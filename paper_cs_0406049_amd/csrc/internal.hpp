@@ -23,11 +23,13 @@ struct RaggedDesc {
 static_assert(sizeof(RaggedDesc) == 48, "descriptor layout");
 
 // A launch shape: threads per workgroup, float4 per thread per loop trip,
-// workgroups (0 = one per tile / unit of work).
+// workgroups (0 = one per tile / unit of work), bytes of LDS each workgroup
+// reserves (0 = none; a reservation caps the workgroups resident per CU).
 struct LaunchShape {
     int block = 256;
     int unroll = 1;
     int grid = 0;
+    int lds = 0;
 };
 
 // Process-wide defaults per form, installed by sincos_set_tuning.
@@ -36,9 +38,12 @@ enum { kFormPlain = 0, kFormRagged = 1 };
 // Built-in defaults (what sincos_set_tuning(NULL) restores).  Plain form: one
 // 64-thread wave per workgroup, one float4 per thread, one tile per
 // workgroup -- the fastest measured shape for its 1-read / 2-write stream on
-// MI355X (3 % ahead of 256 threads).  Ragged form: 256 threads, where the
-// per-unit segment lookup is amortized over more work.
-constexpr LaunchShape kBuiltinShape[2] = {{64, 1, 0}, {256, 1, 0}};
+// MI355X (3 % ahead of 256 threads) -- and 7 KiB of LDS reserved per
+// workgroup, so that at most 22 are resident per CU: fewer tiles in flight
+// keep fewer DRAM rows open at once (1-2 % faster than no cap; a cap below
+// about 20 workgroups starves the reads).  Ragged form: 256 threads, where
+// the per-unit segment lookup is amortized over more work.
+constexpr LaunchShape kBuiltinShape[2] = {{64, 1, 0, 7168}, {256, 1, 0, 0}};
 LaunchShape default_shape(int form);
 int validate_shape(const LaunchShape &sh, const char *who);
 
@@ -58,6 +63,25 @@ hipError_t launch_sincos_interleaved(const float *x, float *out, int64_t n, int 
                                      hipStream_t stream);
 hipError_t launch_copy_ceiling(const float *x, float *s, float *c, int64_t n,
                                const LaunchShape &shape, hipStream_t stream);
+// Memory-traffic probes (probes.hip): the kinds of sincos_stream_probe_f32;
+// policy -1 is the plain kernel's cache policy, else the aux bits of the
+// probe's stores (of its loads for the read probe).
+enum {
+    kProbeRead = 0,
+    kProbeWrite = 1,
+    kProbeWrite1 = 2,
+    kProbeCopy = 3,
+    kProbeCopyBatch = 4,
+    kProbeCopySplit = 5,
+    kProbeCopyLds = 6,
+    kProbeCopyXcd = 7,
+    kProbeCount = 8
+};
+bool probe_takes_policy(int probe);
+bool probe_policy_ok(int policy);
+int probe_block(int probe, const LaunchShape &shape);
+hipError_t launch_stream_probe(int probe, int policy, const float *x, float *s, float *c,
+                               int64_t n, const LaunchShape &shape, hipStream_t stream);
 hipError_t launch_pair_ceiling(const float *x, float *out, int64_t n, int32_t reps,
                                hipStream_t stream);
 hipError_t launch_ragged(const RaggedDesc *desc, const int64_t *ubeg, int32_t count,

@@ -102,9 +102,9 @@ hipError_t launch_plain_am(const float *x, float *s, float *c, int64_t n,
         if (sh.grid > 0)
             grid = std::min<int64_t>(grid, sh.grid);
         grid = std::max<int64_t>(grid, 1);
-#define MI355_SCALAR(UU)                                                                       \
-    hipLaunchKernelGGL((k_sincos_scalar<A, M, UU>), dim3((unsigned)grid), dim3(sh.block), 0, st, \
-                       x, s, c, n)
+#define MI355_SCALAR(UU)                                                                  \
+    hipLaunchKernelGGL((k_sincos_scalar<A, M, UU>), dim3((unsigned)grid), dim3(sh.block),   \
+                       (unsigned)sh.lds, st, x, s, c, n)
         switch (sh.unroll) {
         case 1: MI355_SCALAR(1); break;
         case 2: MI355_SCALAR(2); break;
@@ -121,9 +121,9 @@ hipError_t launch_plain_am(const float *x, float *s, float *c, int64_t n,
     if (sh.grid > 0)
         grid = std::min<int64_t>(grid, sh.grid);
     grid = std::max<int64_t>(grid, 1);
-#define MI355_VEC(UU)                                                                        \
-    hipLaunchKernelGGL((k_sincos_vec<A, M, UU>), dim3((unsigned)grid), dim3(sh.block), 0, st, \
-                       x, s, c, n4, (int)head, tail)
+#define MI355_VEC(UU)                                                                   \
+    hipLaunchKernelGGL((k_sincos_vec<A, M, UU>), dim3((unsigned)grid), dim3(sh.block),   \
+                       (unsigned)sh.lds, st, x, s, c, n4, (int)head, tail)
     switch (sh.unroll) {
     case 1: MI355_VEC(1); break;
     case 2: MI355_VEC(2); break;
@@ -165,9 +165,9 @@ hipError_t launch_copy_ceiling(const float *x, float *s, float *c, int64_t n,
     const f4 *xv = reinterpret_cast<const f4 *>(x);
     f4 *sv = reinterpret_cast<f4 *>(s);
     f4 *cv = reinterpret_cast<f4 *>(c);
-#define MI355_COPY(UU)                                                                     \
-    hipLaunchKernelGGL((k_copy_1r2w<UU>), dim3((unsigned)grid), dim3(sh.block), 0, st, xv, sv, \
-                       cv, n4)
+#define MI355_COPY(UU)                                                                   \
+    hipLaunchKernelGGL((k_copy_1r2w<UU>), dim3((unsigned)grid), dim3(sh.block),           \
+                       (unsigned)sh.lds, st, xv, sv, cv, n4)
     switch (sh.unroll) {
     case 1: MI355_COPY(1); break;
     case 2: MI355_COPY(2); break;

@@ -3,9 +3,9 @@
 // here; every call that passes no launch shape (or 0 in a field) then uses it.
 //
 // The accepted text is a small JSON subset:
-//   {"plain": {"block": 256, "unroll": 1, "grid": 0},
+//   {"plain": {"block": 256, "unroll": 1, "grid": 0, "lds": 8192},
 //    "ragged": {"block": 512, "unroll": 2, "grid": 0}}
-// Both forms and all three fields are optional; a missing field takes the
+// Both forms and all four fields are optional; a missing field takes the
 // built-in default (kBuiltinShape).  Anything else (unknown keys,
 // non-integers, numbers JSON does not allow, escapes in keys, a repeated key,
 // trailing text) is rejected, leaving the current shapes unchanged.
@@ -38,6 +38,8 @@ int validate_shape(const LaunchShape &sh, const char *who)
         return set_error(SINCOS_EINVAL, std::string(who) + ": unroll must be 1, 2, 4 or 8");
     if (sh.grid < 0)
         return set_error(SINCOS_EINVAL, std::string(who) + ": grid must be >= 0");
+    if (sh.lds < 0 || sh.lds > 65536)
+        return set_error(SINCOS_EINVAL, std::string(who) + ": lds must be in [0, 65536]");
     return SINCOS_OK;
 }
 
@@ -108,7 +110,7 @@ struct Reader {
         out = (int)(neg ? -v : v);
         return true;
     }
-    // {"block": B, "unroll": U, "grid": G}, any subset, any order
+    // {"block": B, "unroll": U, "grid": G, "lds": L}, any subset, any order
     bool shape(LaunchShape &sh)
     {
         if (!expect('{'))
@@ -118,19 +120,19 @@ struct Reader {
             ++p;
             return true;
         }
-        bool seen[3] = {false, false, false};
+        bool seen[4] = {false, false, false, false};
         for (;;) {
             std::string k;
             int v = 0;
             if (!key(k) || !expect(':') || !integer(v))
                 return false;
-            const int f = k == "block" ? 0 : k == "unroll" ? 1 : k == "grid" ? 2 : -1;
+            const int f = k == "block" ? 0 : k == "unroll" ? 1 : k == "grid" ? 2 : k == "lds" ? 3 : -1;
             if (f < 0)
                 return fail("unknown field \"" + k + "\"");
             if (seen[f])
                 return fail("repeated field \"" + k + "\"");
             seen[f] = true;
-            (f == 0 ? sh.block : f == 1 ? sh.unroll : sh.grid) = v;
+            (f == 0 ? sh.block : f == 1 ? sh.unroll : f == 2 ? sh.grid : sh.lds) = v;
             ws();
             if (*p == ',') {
                 ++p;
@@ -212,12 +214,13 @@ extern "C" int64_t sincos_get_tuning(char *buf, int64_t cap)
         cur[0] = g_tuned[0];
         cur[1] = g_tuned[1];
     }
-    char text[192];
+    char text[256];
     const int len = std::snprintf(
         text, sizeof text,
-        "{\"plain\": {\"block\": %d, \"unroll\": %d, \"grid\": %d}, "
-        "\"ragged\": {\"block\": %d, \"unroll\": %d, \"grid\": %d}}",
-        cur[0].block, cur[0].unroll, cur[0].grid, cur[1].block, cur[1].unroll, cur[1].grid);
+        "{\"plain\": {\"block\": %d, \"unroll\": %d, \"grid\": %d, \"lds\": %d}, "
+        "\"ragged\": {\"block\": %d, \"unroll\": %d, \"grid\": %d, \"lds\": %d}}",
+        cur[0].block, cur[0].unroll, cur[0].grid, cur[0].lds, cur[1].block, cur[1].unroll,
+        cur[1].grid, cur[1].lds);
     if (len < 0 || len >= (int)sizeof text)
         return set_error(SINCOS_EINVAL, "sincos_get_tuning: formatting failed");
     if (buf && cap > 0) {

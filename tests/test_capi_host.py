@@ -239,25 +239,33 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
 
 def test_tuning_round_trip_and_rejection(L):
     from paper_cs_0406049_amd import autotune
-    builtin = {"plain": {"block": 64, "unroll": 1, "grid": 0},
-               "ragged": {"block": 256, "unroll": 1, "grid": 0}}
+    builtin = {"plain": {"block": 64, "unroll": 1, "grid": 0, "lds": 7168},
+               "ragged": {"block": 256, "unroll": 1, "grid": 0, "lds": 0}}
     try:
         _capi.set_tuning(None)
         assert _capi.get_tuning() == builtin
         autotune.install("ragged", (512, 2, 4096))
-        want = {"plain": builtin["plain"], "ragged": {"block": 512, "unroll": 2, "grid": 4096}}
+        want = {"plain": builtin["plain"],
+                "ragged": {"block": 512, "unroll": 2, "grid": 4096, "lds": 0}}
         assert _capi.get_tuning() == want
+        autotune.install("ragged", (64, 1, 1 << 30, 6656))
+        assert _capi.get_tuning()["ragged"] == {"block": 64, "unroll": 1, "grid": 1 << 30,
+                                                "lds": 6656}
+        autotune.install("ragged", (64, 1, 1 << 30, -1))       # -1: no reservation
+        assert _capi.get_tuning()["ragged"]["lds"] == 0
         # a form left out of the text gets the built-in shape back
         _capi.set_tuning({"plain": {"unroll": 4}})
-        assert _capi.get_tuning() == {"plain": {"block": 64, "unroll": 4, "grid": 0},
+        assert _capi.get_tuning() == {"plain": {"block": 64, "unroll": 4, "grid": 0, "lds": 7168},
                                       "ragged": builtin["ragged"]}
-        _capi.set_tuning({"plain": (512, 2, 0), "ragged": (1024, 8, 7)})
+        _capi.set_tuning({"plain": (512, 2, 0, 0), "ragged": (1024, 8, 7, 65536)})
         kept = _capi.get_tuning()
+        assert kept["ragged"]["lds"] == 65536 and kept["plain"]["lds"] == 0
         for bad in (b'{"plain": {"block": 100}}', b'{"plain": {"unroll": 3}}',
                     b'{"ragged": {"grid": -1}}', b'{"plan": {}}', b'{"plain": {"block": 1.5}}',
                     b'{"plain": {"block": 256', b'{} x', b'[]', b'{"plain": {"warps": 4}}',
                     b'{"plain": {"block": 99999999999}}', b'{"plain": {"grid": 2147483648}}',
-                    b''):
+                    b'{"plain": {"lds": -1}}', b'{"ragged": {"lds": 65537}}',
+                    b'{"plain": {"lds": 1, "lds": 2}}', b''):
             assert L.sincos_set_tuning(bad) == _capi.EINVAL, bad
             assert "sincos_set_tuning" in _capi.last_error()
             assert _capi.get_tuning() == kept, bad

@@ -94,19 +94,20 @@ def test_ragged_aliasing_matches_brute_force(L):
 
 # --- tuning parser -------------------------------------------------------
 
-BUILTIN = {"plain": {"block": 64, "unroll": 1, "grid": 0},
-           "ragged": {"block": 256, "unroll": 1, "grid": 0}}
+BUILTIN = {"plain": {"block": 64, "unroll": 1, "grid": 0, "lds": 7168},
+           "ragged": {"block": 256, "unroll": 1, "grid": 0, "lds": 0}}
 
-field = st.sampled_from(["block", "unroll", "grid"])
-value = st.one_of(st.sampled_from([0, 1, 2, 4, 8, 64, 128, 192, 256, 512, 1024, 1088, 3, 65]),
+field = st.sampled_from(["block", "unroll", "grid", "lds"])
+value = st.one_of(st.sampled_from([0, 1, 2, 4, 8, 64, 128, 192, 256, 512, 1024, 1088, 3, 65,
+                                   65536, 65537]),
                   st.integers(-5, 2000), st.integers(-(1 << 40), 1 << 40))
-shape = st.dictionaries(field, value, max_size=3)
+shape = st.dictionaries(field, value, max_size=4)
 document = st.dictionaries(st.sampled_from(["plain", "ragged"]), shape, max_size=2)
 
 
 def valid_shape(sh):
     return (64 <= sh["block"] <= 1024 and sh["block"] % 64 == 0 and sh["unroll"] in (1, 2, 4, 8)
-            and sh["grid"] >= 0)
+            and sh["grid"] >= 0 and 0 <= sh["lds"] <= 65536)
 
 
 @settings(max_examples=400, deadline=None)
@@ -141,7 +142,7 @@ def test_tuning_accepts_exactly_the_valid_documents(L, doc, indent):
 @example(text='{"plain": {"block": 1e2}}')
 @example(text='{"ragged": {"block": 128}, "ragged": {"grid": 1}}')
 @example(text='{"plain": {"block": 128, "block": 64}}')
-@given(text=st.text(alphabet='{}[]:,"-. 0123456789eE\t\x0b\x0cplainraggedblockunrollgridx\\',
+@given(text=st.text(alphabet='{}[]:,"-. 0123456789eE\t\x0b\x0cplainraggedblockunrollgridldsx\\',
                     max_size=80))
 def test_tuning_parser_never_accepts_what_json_rejects(L, text):
     """Arbitrary text: the call returns OK or EINVAL and never crashes; it is

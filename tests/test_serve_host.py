@@ -200,8 +200,20 @@ def test_autotune_cache_keys_and_candidates(tmp_path):
     k3 = autotune.cache_key("gfx950", 256, 4096, 453_000_000, 1, 0)
     assert k1 == k2 and k1 != k3
     cands = list(autotune.candidates(256))
-    assert len(cands) == len(autotune.BLOCKS) * len(autotune.UNROLLS) * len(autotune.WAVES_PER_CU)
-    assert all(b % 64 == 0 and u in (1, 2, 4, 8) and g >= 1 for b, u, g in cands)
+    persistent = [w for w in autotune.WAVES_PER_CU if w]
+    capped = [(b, cap) for b in autotune.BLOCKS for cap in autotune.WAVE_CAPS
+              if autotune.lds_for_cap(b, cap) is not None]
+    assert len(cands) == len(autotune.UNROLLS) * (len(autotune.BLOCKS) * len(persistent) +
+                                                 len(capped))
+    assert len(set(cands)) == len(cands)
+    assert all(b % 64 == 0 and u in (1, 2, 4, 8) and g >= 1 and (l == -1 or 0 < l <= 65536)
+               for b, u, g, l in cands)
+    # an LDS reservation holds a CU to at least the capped number of waves
+    for b, u, g, l in cands:
+        if l > 0:
+            assert g == autotune.COVER
+            waves = (autotune.LDS_PER_CU // l) * (b // 64)
+            assert min(autotune.WAVE_CAPS[1:]) <= waves <= 2 * max(autotune.WAVE_CAPS), (b, l)
     p = str(tmp_path / "t.json")
     autotune.save_cache({k1: {"shape": [256, 4, 2048]}}, p)
     assert autotune.load_cache(p)[k1]["shape"] == [256, 4, 2048]
