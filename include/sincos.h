@@ -286,6 +286,17 @@ SINCOS_API int sinusoid_f32_fit_step_noalloc(const float *t, const float *y_obs,
 SINCOS_API int huygens_f32(const float *xo, const float *yo, int64_t P, const float *src,
                            int32_t S, float k, float L, float *re, float *im, void *stream);
 
+/* Measurement helper: the Huygens term's own ceiling.  Exactly huygens_f32
+ * over the 8 sources of src8 ([8][4] = (x, y, a, phi), device, 16-byte
+ * aligned) repeated `reps` times (S = 8 * reps, sources in table order
+ * within each repetition): the same kernel code as huygens_f32 with the
+ * source index wrapped into the 8-entry table, which stays in the scalar
+ * cache, i.e. the term's arithmetic with (almost) no source traffic.  Same
+ * argument rules as huygens_f32; reps outside [0, 2^28) is EINVAL.        */
+SINCOS_API int huygens_term_ceiling_f32(const float *xo, const float *yo, int64_t P,
+                                        const float *src8, int32_t reps, float k, float L,
+                                        float *re, float *im, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Measurement helper: the same memory traffic as the plain form (read 4 B,
  * write 8 B per element, float4 body, same launch shape) with no
@@ -393,10 +404,13 @@ SINCOS_API int sincos_f32_doublings(const float *x, float *s, float *c, int64_t 
  * `max_inflight` streams.  Submitted requests queue in arrival order; a
  * request is admitted when its 12 n bytes fit in the HBM budget (4 n for the
  * input it pins, 8 n for its outputs) and an arena block is free.  Whenever
- * a stream is free, every admitted request not yet launched (up to the
- * batch caps) goes to the device as ONE ragged launch, so requests that
- * arrive while others run join the next batch and batches overlap on the
- * device.  A completion carries the device addresses of the request's
+ * a stream is free, the admitted requests not yet launched go to the device
+ * as ONE ragged launch (up to the batch caps), so requests that arrive while
+ * others run join the next batch and batches overlap on the device.  With a
+ * size split, requests of more than split_elems elements and smaller ones
+ * never share a batch: the oldest waiting request decides the class, and
+ * the batch takes the waiting requests of that class in arrival order, so a
+ * small request never waits for a large one's batch to finish.  A completion carries the device addresses of the request's
  * outputs; they stay valid until the request is released (or at once with
  * auto_release).  Release returns the request's budget and arena block.
  * Each result is the same bits as a plain sincos_f32 call on the same input
@@ -420,6 +434,8 @@ typedef struct {
     int64_t sim_elem_ps;        /* simulated: picoseconds per element                   */
     int32_t sim_fail_every;     /* simulated: every k-th batch fails (0 = never)        */
     int32_t auto_release;       /* 1 = free a request's outputs as soon as it completes */
+    int64_t split_elems;        /* size split between batch classes (0 = 2^21 elements,
+                                   -1 = no split: one class)                            */
 } sincos_server_config_t;
 
 typedef struct {

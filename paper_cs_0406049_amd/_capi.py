@@ -47,7 +47,7 @@ class ServerConfig(ctypes.Structure):
                 ("arith", ctypes.c_int32), ("method", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("executor", ctypes.c_int32), ("sim_batch_ns", ctypes.c_int64),
                 ("sim_elem_ps", ctypes.c_int64), ("sim_fail_every", ctypes.c_int32),
-                ("auto_release", ctypes.c_int32)]
+                ("auto_release", ctypes.c_int32), ("split_elems", ctypes.c_int64)]
 
 
 class Completion(ctypes.Structure):
@@ -112,6 +112,8 @@ _SIGNATURES = {
                                             ctypes.POINTER(ctypes.c_float), _I32, _I32, _P]),
     "huygens_f32": (ctypes.c_int, [_P, _P, _I64, _P, _I32, ctypes.c_float, ctypes.c_float, _P, _P,
                                    _P]),
+    "huygens_term_ceiling_f32": (ctypes.c_int, [_P, _P, _I64, _P, _I32, ctypes.c_float,
+                                                ctypes.c_float, _P, _P, _P]),
     "sincos_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)]),
     "sincos_server_submit": (ctypes.c_int, [_P, _P, _I64, ctypes.c_uint64, ctypes.POINTER(_I64)]),
     "sincos_server_submit_on": (ctypes.c_int, [_P, _P, _I64, ctypes.c_uint64, _P,
@@ -493,6 +495,15 @@ def huygens_f32(xo, yo, src, k, L, re, im, P=None, S=None, stream=None) -> None:
     S = int(S if S is not None else src.numel() // 4)
     _check(lib().huygens_f32(_ptr(xo, P), _ptr(yo, P), P, _ptr(src, 4 * S), S, float(k),
                              float(L), _ptr(re, P), _ptr(im, P), _stream(stream)))
+
+
+def huygens_term_ceiling_f32(xo, yo, src8, reps, k, L, re, im, P=None, stream=None) -> None:
+    """huygens_f32 over the 8 sources of src8 repeated reps times, the
+    sources held in registers (the term's ceiling)."""
+    P = _numel(xo, P)
+    _check(lib().huygens_term_ceiling_f32(_ptr(xo, P), _ptr(yo, P), P, _ptr(src8, 32), int(reps),
+                                          float(k), float(L), _ptr(re, P), _ptr(im, P),
+                                          _stream(stream)))
 
 
 def set_tuning(shapes) -> None:

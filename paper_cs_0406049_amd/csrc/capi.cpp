@@ -1107,36 +1107,61 @@ extern "C" int sinusoid_f32_fit_step_noalloc(const float *t, const float *y_obs,
                            : hip_error(e, "sinusoid_f32_fit_step_noalloc: kernel launch");
 }
 
+// Checks shared by the Huygens sum and its term ceiling (S sources in src).
+static int check_huygens(const float *xo, const float *yo, int64_t P, const float *src, int64_t S,
+                         float L, const float *re, const float *im, const std::string &who)
+{
+    if (P < 0 || S < 0)
+        return set_error(SINCOS_EINVAL, who + ": P < 0 or S < 0");
+    if (P > (int64_t(1) << 36))  // beyond any device memory
+        return set_error(SINCOS_EINVAL, who + ": P too large");
+    if (P == 0)
+        return SINCOS_OK;
+    if (!xo || !yo || !re || !im || (S > 0 && !src))
+        return set_error(SINCOS_EINVAL, who + ": null pointer");
+    if (!aligned4(xo) || !aligned4(yo) || !aligned4(re) || !aligned4(im) ||
+        (S > 0 && (reinterpret_cast<uintptr_t>(src) & 15)))
+        return set_error(SINCOS_EINVAL, who + ": arrays must be 4-byte aligned, src 16-byte aligned");
+    if (!(L > 0.0f) || !(L < 1e18f))
+        return set_error(SINCOS_EINVAL, who + ": L must be positive and finite");
+    if (ranges_overlap(re, P, im, P) || ranges_overlap(re, P, xo, P) ||
+        ranges_overlap(re, P, yo, P) || ranges_overlap(im, P, xo, P) ||
+        ranges_overlap(im, P, yo, P) ||
+        (S > 0 && (ranges_overlap(re, P, src, 4 * S) || ranges_overlap(im, P, src, 4 * S))))
+        return set_error(SINCOS_EOVERLAP, who + ": outputs overlap inputs or each other");
+    return SINCOS_OK;
+}
+
 extern "C" int huygens_f32(const float *xo, const float *yo, int64_t P, const float *src,
                            int32_t S, float k, float L, float *re, float *im, void *stream)
 {
     clear_error();
-    if (P < 0 || S < 0)
-        return set_error(SINCOS_EINVAL, "huygens_f32: P < 0 or S < 0");
-    if (P == 0)
-        return SINCOS_OK;
-    if (P > (int64_t(1) << 36))  // beyond any device memory
-        return set_error(SINCOS_EINVAL, "huygens_f32: P too large");
-    if (!xo || !yo || !re || !im || (S > 0 && !src))
-        return set_error(SINCOS_EINVAL, "huygens_f32: null pointer");
-    if (!aligned4(xo) || !aligned4(yo) || !aligned4(re) || !aligned4(im) ||
-        (S > 0 && (reinterpret_cast<uintptr_t>(src) & 15)))
-        return set_error(SINCOS_EINVAL,
-                         "huygens_f32: arrays must be 4-byte aligned, src 16-byte aligned");
-    if (!(L > 0.0f) || !(L < 1e18f))
-        return set_error(SINCOS_EINVAL, "huygens_f32: L must be positive and finite");
-    if (ranges_overlap(re, P, im, P) || ranges_overlap(re, P, xo, P) ||
-        ranges_overlap(re, P, yo, P) || ranges_overlap(im, P, xo, P) ||
-        ranges_overlap(im, P, yo, P) ||
-        (S > 0 && (ranges_overlap(re, P, src, 4 * (int64_t)S) ||
-                   ranges_overlap(im, P, src, 4 * (int64_t)S))))
-        return set_error(SINCOS_EOVERLAP, "huygens_f32: outputs overlap inputs or each other");
+    int rc = check_huygens(xo, yo, P, src, S, L, re, im, "huygens_f32");
+    if (rc != SINCOS_OK || P == 0)
+        return rc;
     const DeviceInfo *dev;
-    int rc;
     if ((rc = current_device(&dev)) != SINCOS_OK)
         return rc;
     hipError_t e = launch_huygens(xo, yo, P, src, S, k, L, re, im, (hipStream_t)stream);
     return e == hipSuccess ? SINCOS_OK : hip_error(e, "huygens_f32: kernel launch");
+}
+
+extern "C" int huygens_term_ceiling_f32(const float *xo, const float *yo, int64_t P,
+                                        const float *src8, int32_t reps, float k, float L,
+                                        float *re, float *im, void *stream)
+{
+    clear_error();
+    if (reps < 0 || reps >= (1 << 28))
+        return set_error(SINCOS_EINVAL, "huygens_term_ceiling_f32: reps must be in [0, 2^28)");
+    int rc = check_huygens(xo, yo, P, src8, kHuygensCeilingSources, L, re, im,
+                           "huygens_term_ceiling_f32");
+    if (rc != SINCOS_OK || P == 0)
+        return rc;
+    const DeviceInfo *dev;
+    if ((rc = current_device(&dev)) != SINCOS_OK)
+        return rc;
+    hipError_t e = launch_huygens_ceiling(xo, yo, P, src8, reps, k, L, re, im, (hipStream_t)stream);
+    return e == hipSuccess ? SINCOS_OK : hip_error(e, "huygens_term_ceiling_f32: kernel launch");
 }
 
 // ---------------------------------------------------------------------------

@@ -575,10 +575,17 @@ __device__ __forceinline__ void huygens_term(float px, float py, f4 sq, float k,
     im = __builtin_fmaf(w, sv, im);
 }
 
+// WRAP = 0: source j is src[j] (the sum).  WRAP = 8: source j is src[j % 8],
+// the term's own ceiling: the same code with the sources served from an
+// 8-entry table that stays in the scalar cache, i.e. the arithmetic with
+// (almost) no source traffic.
+template <int WRAP>
 __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *yo, int64_t P,
                                                  const f4 *__restrict__ src, int32_t S, float k,
                                                  float L, float L2, float *re, float *im)
 {
+    static_assert(WRAP == 0 || WRAP % kHuyGroup == 0, "groups stay within the table");
+    auto at = [](int32_t j) { return WRAP ? (j & (WRAP - 1)) : j; };
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i - threadIdx.x < P;
          i += stride) {  // block-uniform loop condition
@@ -590,7 +597,7 @@ __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *y
         if (full > 0) {
 #pragma unroll
             for (int u = 0; u < kHuyGroup; ++u)
-                cur[u] = src[u];
+                cur[u] = src[at(u)];
         }
         for (int32_t q = 0; q < full; q += kHuyGroup) {
             // the next group; the last group reloads itself, so every index is < S
@@ -598,7 +605,7 @@ __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *y
             f4 nxt[kHuyGroup];
 #pragma unroll
             for (int u = 0; u < kHuyGroup; ++u)
-                nxt[u] = src[nq + u];
+                nxt[u] = src[at(nq + u)];
 #pragma unroll
             for (int u = 0; u < kHuyGroup; ++u)
                 huygens_term(px, py, cur[u], k, L, L2, ar, ai);
@@ -607,7 +614,7 @@ __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *y
                 cur[u] = nxt[u];
         }
         for (int32_t q = full; q < S; ++q)
-            huygens_term(px, py, src[q], k, L, L2, ar, ai);
+            huygens_term(px, py, src[at(q)], k, L, L2, ar, ai);
         if (i < P) {
             re[i] = ar;
             im[i] = ai;
@@ -862,8 +869,22 @@ hipError_t launch_huygens(const float *xo, const float *yo, int64_t P, const flo
     const int64_t grid = std::min<int64_t>(std::max<int64_t>(1, (P + per_block - 1) / per_block),
                                            int64_t(1) << 20);
     const float L2 = L * L;
-    hipLaunchKernelGGL(k_huygens, dim3((unsigned)grid), dim3(256), 0, st, xo, yo, P,
+    hipLaunchKernelGGL(k_huygens<0>, dim3((unsigned)grid), dim3(256), 0, st, xo, yo, P,
                        reinterpret_cast<const f4 *>(src), S, k, L, L2, re, im);
+    return hipGetLastError();
+}
+
+hipError_t launch_huygens_ceiling(const float *xo, const float *yo, int64_t P, const float *src,
+                                  int32_t reps, float k, float L, float *re, float *im,
+                                  hipStream_t st)
+{
+    const int64_t per_block = 256;
+    const int64_t grid = std::min<int64_t>(std::max<int64_t>(1, (P + per_block - 1) / per_block),
+                                           int64_t(1) << 20);
+    const int64_t S = (int64_t)kHuygensCeilingSources * reps;  // below 2^31: reps < 2^28
+    hipLaunchKernelGGL(k_huygens<kHuygensCeilingSources>, dim3((unsigned)grid), dim3(256), 0, st,
+                       xo, yo, P, reinterpret_cast<const f4 *>(src), (int32_t)S, k, L, L * L, re,
+                       im);
     return hipGetLastError();
 }
 

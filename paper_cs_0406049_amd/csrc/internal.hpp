@@ -119,6 +119,11 @@ hipError_t launch_sinusoid_residual(const float *t, const float *y_obs, int64_t 
                                     float *loss, float *part, hipStream_t stream);
 hipError_t launch_huygens(const float *xo, const float *yo, int64_t P, const float *src,
                           int32_t S, float k, float L, float *re, float *im, hipStream_t stream);
+// The Huygens term over 8 register-resident sources, `reps` passes.
+constexpr int kHuygensCeilingSources = 8;
+hipError_t launch_huygens_ceiling(const float *xo, const float *yo, int64_t P, const float *src,
+                                  int32_t reps, float k, float L, float *re, float *im,
+                                  hipStream_t stream);
 int64_t sinusoid_chunks(int64_t N);
 int64_t sinusoid_parts(int64_t N);
 int64_t sinusoid_kgroups(int32_t K);

@@ -320,6 +320,35 @@ struct sincos_server {
         }
     }
 
+    // Move the next batch out of `admitted` (scheduler thread): in arrival
+    // order up to the caps, and with a size split only requests of the
+    // oldest one's class (the others keep their places).
+    void form_batch(std::vector<Request *> &batch)
+    {
+        batch.clear();
+        const size_t cap = cfg.mode == 1 ? 1 : (size_t)cfg.max_batch_requests;
+        const bool split = cfg.split_elems > 0;
+        const bool large = split && admitted.front()->n > cfg.split_elems;
+        int64_t elems = 0;
+        size_t keep = 0, j = 0;
+        for (; j < admitted.size() && batch.size() < cap; ++j) {
+            Request *r = admitted[j];
+            const bool fits = !split || (r->n > cfg.split_elems) == large;
+            if (fits && !batch.empty() && cfg.max_batch_elems > 0 &&
+                elems + r->n > cfg.max_batch_elems)
+                break;
+            if (fits) {
+                elems += r->n;
+                batch.push_back(r);
+            } else {
+                admitted[keep++] = r;
+            }
+        }
+        for (; j < admitted.size(); ++j)
+            admitted[keep++] = admitted[j];
+        admitted.resize(keep);
+    }
+
     // Check the device; complete the requests of finished batches.
     // Returns the number of batches still running.
     int reap(bool *progressed)
@@ -409,18 +438,8 @@ struct sincos_server {
                 Slot &sl = slots[k];
                 if (sl.busy)
                     continue;
-                size_t take = 0;
-                int64_t elems = 0;
-                const size_t cap = cfg.mode == 1 ? 1 : (size_t)cfg.max_batch_requests;
-                while (take < admitted.size() && take < cap) {
-                    if (take > 0 && cfg.max_batch_elems > 0 &&
-                        elems + admitted[take]->n > cfg.max_batch_elems)
-                        break;
-                    elems += admitted[take]->n;
-                    ++take;
-                }
-                sl.batch.assign(admitted.begin(), admitted.begin() + take);
-                admitted.erase(admitted.begin(), admitted.begin() + take);
+                form_batch(sl.batch);
+                const size_t take = sl.batch.size();
                 const int64_t t = now_ns();
                 for (Request *r : sl.batch) {
                     r->t_launch = t;
@@ -477,8 +496,11 @@ extern "C" int sincos_server_create(const sincos_server_config_t *cfg, sincos_se
     *out = nullptr;
     sincos_server_config_t c = *cfg;
     if (c.budget_bytes < 0 || c.max_inflight < 0 || c.max_batch_requests < 0 ||
-        c.max_batch_elems < 0 || c.sim_batch_ns < 0 || c.sim_elem_ps < 0 || c.sim_fail_every < 0)
+        c.max_batch_elems < 0 || c.sim_batch_ns < 0 || c.sim_elem_ps < 0 || c.sim_fail_every < 0 ||
+        c.split_elems < -1)
         return set_error(SINCOS_EINVAL, "server_create: negative setting");
+    if (c.split_elems == 0)
+        c.split_elems = int64_t(1) << 21;
     if (c.budget_bytes == 0)
         c.budget_bytes = int64_t(8) << 30;
     if (c.max_inflight == 0)

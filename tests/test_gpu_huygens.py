@@ -76,3 +76,29 @@ def test_validation(torch_dev):
         _capi.huygens_f32(x, x, src, 1.0, 10.0, out, out)           # re == im
     with pytest.raises(_capi.SincosError):
         _capi.huygens_f32(x, x, src[1:].data_ptr(), 1.0, 10.0, out, out2, 8, 3)  # src misaligned
+
+
+@pytest.mark.parametrize("P,reps", [(1, 1), (4099, 3), (777, 0), (300, 17)])
+def test_term_ceiling_is_the_sum_over_the_repeated_table(torch_dev, P, reps):
+    """huygens_term_ceiling_f32 computes huygens_f32 over its 8 sources
+    repeated reps times: bit-exact against the oracle on the tiled table."""
+    torch = torch_dev
+    from paper_cs_0406049_amd import _capi, workloads
+    p = workloads.huygens_problem(screen_side=64, aperture_side=8, seed=P + reps)
+    rng = np.random.default_rng(P)
+    idx = rng.choice(p.xo.size, min(P, p.xo.size), replace=False)
+    xo = np.resize(p.xo[idx], P).astype(np.float32)
+    yo = np.resize(p.yo[idx], P).astype(np.float32)
+    src8 = np.ascontiguousarray(p.src[rng.choice(p.src.shape[0], 8, replace=False)])
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()  # noqa: E731
+    xd, yd, sd = d(xo), d(yo), d(src8.reshape(-1))
+    re = torch.full_like(xd, float("nan"))
+    im = torch.full_like(xd, float("nan"))
+    _capi.huygens_term_ceiling_f32(xd, yd, sd, reps, p.k, p.L, re, im)
+    torch.cuda.synchronize()
+    tiled = np.tile(src8, (reps, 1)) if reps else np.zeros((0, 4), np.float32)
+    ro, io = oracle.huygens(xo, yo, tiled, p.k, p.L, threads=oracle.default_threads())
+    assert_bit_exact(re.cpu().numpy(), ro, "ceiling re P=%d reps=%d" % (P, reps))
+    assert_bit_exact(im.cpu().numpy(), io, "ceiling im P=%d reps=%d" % (P, reps))
+    with pytest.raises(_capi.SincosError):
+        _capi.huygens_term_ceiling_f32(xd, yd, sd, -1, p.k, p.L, re, im)

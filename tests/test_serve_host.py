@@ -136,6 +136,33 @@ def test_batch_caps():
         assert out["batch_requests"].max() <= 2
 
 
+def test_size_split_never_mixes_classes_in_a_batch():
+    """With a size split, a batch holds only requests above the split or
+    only requests at or below it; the oldest waiting request picks the class
+    and each class keeps its arrival order.  split_elems -1 mixes them."""
+    sizes = np.array([5000, 10, 20, 6000, 30, 7000, 40, 50, 8000, 60] * 6, np.int64)
+    for split, mixed_ok in ((1000, False), (-1, True)):
+        with sim(max_inflight=1, sim_batch_ns=200_000, auto_release=True,
+                 split_elems=split) as s:
+            # the first request occupies the one slot while the rest queue up
+            out = s.replay([FAKE] * sizes.size, sizes, np.zeros(sizes.size, np.int64))
+        assert np.all(out["status"] == 0)
+        mixed = False
+        for t in np.unique(out["t_launch_ns"]):
+            members = np.flatnonzero(out["t_launch_ns"] == t)
+            big = sizes[members] > 1000
+            mixed |= bool(big.any() and not big.all())
+            # within a batch, requests keep their arrival order
+            assert np.all(np.diff(out["t_submit_ns"][members]) >= 0)
+        assert mixed == mixed_ok, (split, mixed)
+        if not mixed_ok:
+            # each class is launched in arrival order
+            for cls in (sizes > 1000, sizes <= 1000):
+                assert np.all(np.diff(out["t_launch_ns"][cls]) >= 0)
+    with pytest.raises(_capi.SincosError):
+        sim(split_elems=-2)
+
+
 def test_per_request_mode_one_launch_each():
     with sim(mode=serve.MODE_PER_REQUEST, sim_batch_ns=5000, auto_release=True) as s:
         out = s.replay([FAKE] * 50, np.full(50, 100, np.int64), np.zeros(50, np.int64))
