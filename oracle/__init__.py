@@ -98,6 +98,8 @@ def lib():
             L.oracle_constants.argtypes = [c_int, fp]
             L.oracle_huygens_f32.argtypes = [fp, fp, i64, fp, i32, ctypes.c_float, ctypes.c_float,
                                              fp, fp, c_int, c_int, c_int]
+            L.oracle_huygens_blocks_f32.argtypes = [fp, fp, i64, fp, i32, i32, ctypes.c_float,
+                                                    ctypes.c_float, fp, fp, c_int, c_int, c_int]
             _lib = L
     return _lib
 
@@ -308,19 +310,25 @@ def sinusoid_adjoint(t, g, A, w, phi, arith: int = FUSED, method: int = METHOD1)
     return dict(gA=gA, gw=gw, gphi=gphi, abs_A=aA, abs_w=aw, abs_phi=aphi)
 
 
+HUYGENS_BLOCKS = 4
+
+
 def huygens(xo, yo, src, k: float, L: float, arith: int = FUSED, method: int = METHOD1,
-            threads: int = 1):
+            threads: int = 1, blocks: int = HUYGENS_BLOCKS):
     """Field (re, im) at screen points (xo, yo, L) from point sources
-    src[S, 4] = (x, y, amplitude, phase); binary32, sources summed in order."""
+    src[S, 4] = (x, y, amplitude, phase); binary32.  The sources are split
+    into `blocks` contiguous blocks of ceil(S / blocks), each summed in source
+    order, and the block sums are added in block order (blocks=1: the plain
+    sum in source order)."""
     xo, yo = _c32(xo), _c32(yo)
     src = np.ascontiguousarray(src, np.float32).reshape(-1, 4)
     re = np.empty_like(xo)
     im = np.empty_like(xo)
-    rc = lib().oracle_huygens_f32(_f32p(xo), _f32p(yo), xo.size, _f32p(src), src.shape[0],
-                                  np.float32(k), np.float32(L), _f32p(re), _f32p(im), arith,
-                                  method, threads)
+    rc = lib().oracle_huygens_blocks_f32(_f32p(xo), _f32p(yo), xo.size, _f32p(src),
+                                         src.shape[0], int(blocks), np.float32(k), np.float32(L),
+                                         _f32p(re), _f32p(im), arith, method, threads)
     if rc != 0:
-        raise ValueError("oracle_huygens_f32 failed")
+        raise ValueError("oracle_huygens_blocks_f32 failed")
     return re, im
 
 

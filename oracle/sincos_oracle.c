@@ -759,53 +759,92 @@ int oracle_sinusoid_adjoint_f64(const float *t, const float *g, int64_t N, const
  *     U_i = sum_j (a_j / r_ij) exp(i (k (r_ij - L) + phi_j)),
  * with the obliquity factor taken as 1 and the path difference r - L
  * written as rho^2 / (r + L) so that no cancellation occurs.  In binary32,
- * sources in order j = 0..S-1, accumulators starting at +0:
+ * for one block of sources j = lo..hi-1 in order, accumulators from +0:
  *     dx = xo - xa;  dy = yo - ya;  rho2 = fmaf(dx, dx, dy * dy)
  *     r = sqrtf(rho2 + L2) with L2 = L * L;  d = rho2 / (r + L)
  *     theta = fmaf(k, d, phi);  (s, c) = the pair of theta
  *     w = a / r;  re = fmaf(w, c, re);  im = fmaf(w, s, im)
- * src holds (xa, ya, a, phi) per source.                                   */
+ * The sum over all S sources splits them into `blocks` contiguous blocks of
+ * ceil(S / blocks) sources (the last ones shorter or empty), sums each block
+ * as above and adds the block sums in block order, (((B0 + B1) + B2) + ...),
+ * re and im separately.  oracle_huygens_f32 is this with 4 blocks (the
+ * order is not in the paper; four blocks let four GPU lanes share a point);
+ * one block is the plain sum in source order.  src holds (xa, ya, a, phi)
+ * per source.                                                               */
+#define HUYGENS_BLOCKS 4
+
 struct huygens_job {
     const float *xo, *yo, *src;
-    int32_t S;
+    int32_t S, blocks;
     float k, L;
     float *re, *im;
     int arith, method;
 };
 
+static void huygens_block_sum(const struct huygens_job *j, int64_t i, int32_t lo, int32_t hi,
+                              float *re_out, float *im_out)
+{
+    const float L2 = j->L * j->L;
+    float re = 0.0f, im = 0.0f;
+    for (int32_t q = lo; q < hi; q++) {
+        const float *sq = j->src + 4 * (int64_t)q;
+        float dx = j->xo[i] - sq[0];
+        float dy = j->yo[i] - sq[1];
+        float dy2 = dy * dy;
+        float rho2 = fmaf(dx, dx, dy2);
+        float r = sqrtf(rho2 + L2);
+        float d = rho2 / (r + j->L);
+        float theta = fmaf(j->k, d, sq[3]);
+        float sv, cv;
+        oracle_sincos_pair(theta, j->arith, j->method, &sv, &cv);
+        float w = sq[2] / r;
+        re = fmaf(w, cv, re);
+        im = fmaf(w, sv, im);
+    }
+    *re_out = re;
+    *im_out = im;
+}
+
 static void huygens_chunk(void *job, int64_t lo, int64_t hi)
 {
     struct huygens_job *j = (struct huygens_job *)job;
-    const float L2 = j->L * j->L;
+    const int32_t per = (int32_t)(((int64_t)j->S + j->blocks - 1) / j->blocks);
     for (int64_t i = lo; i < hi; i++) {
         float re = 0.0f, im = 0.0f;
-        for (int32_t q = 0; q < j->S; q++) {
-            const float *sq = j->src + 4 * (int64_t)q;
-            float dx = j->xo[i] - sq[0];
-            float dy = j->yo[i] - sq[1];
-            float dy2 = dy * dy;
-            float rho2 = fmaf(dx, dx, dy2);
-            float r = sqrtf(rho2 + L2);
-            float d = rho2 / (r + j->L);
-            float theta = fmaf(j->k, d, sq[3]);
-            float sv, cv;
-            oracle_sincos_pair(theta, j->arith, j->method, &sv, &cv);
-            float w = sq[2] / r;
-            re = fmaf(w, cv, re);
-            im = fmaf(w, sv, im);
+        for (int32_t b = 0; b < j->blocks; b++) {
+            const int32_t first = (int32_t)(b * (int64_t)per < j->S ? b * (int64_t)per : j->S);
+            const int32_t last = (int32_t)(first + (int64_t)per < j->S ? first + per : j->S);
+            float bre, bim;
+            huygens_block_sum(j, i, first, last, &bre, &bim);
+            if (b == 0) {
+                re = bre;
+                im = bim;
+            } else {
+                re = re + bre;
+                im = im + bim;
+            }
         }
         j->re[i] = re;
         j->im[i] = im;
     }
 }
 
+int oracle_huygens_blocks_f32(const float *xo, const float *yo, int64_t P, const float *src,
+                              int32_t S, int32_t blocks, float k, float L, float *re, float *im,
+                              int arith, int method, int threads)
+{
+    if (P < 0 || S < 0 || blocks < 1 || (P > 0 && (!xo || !yo || !re || !im)) ||
+        (S > 0 && !src))
+        return -1;
+    struct huygens_job j = {xo, yo, src, S, blocks, k, L, re, im, arith, method};
+    return run_chunks(huygens_chunk, &j, P, threads);
+}
+
 int oracle_huygens_f32(const float *xo, const float *yo, int64_t P, const float *src, int32_t S,
                        float k, float L, float *re, float *im, int arith, int method, int threads)
 {
-    if (P < 0 || S < 0 || (P > 0 && (!xo || !yo || !re || !im)) || (S > 0 && !src))
-        return -1;
-    struct huygens_job j = {xo, yo, src, S, k, L, re, im, arith, method};
-    return run_chunks(huygens_chunk, &j, P, threads);
+    return oracle_huygens_blocks_f32(xo, yo, P, src, S, HUYGENS_BLOCKS, k, L, re, im, arith,
+                                     method, threads);
 }
 
 /* Constants as the oracle rounds them, for the bit-pattern test.           */

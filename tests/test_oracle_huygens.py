@@ -1,9 +1,12 @@
 """Pins of the oracle's Huygens point-source sum: a single source in closed
 form, the exact double-precision model within a derived bound, the
-Fraunhofer (far-field) limit of a square aperture, and symmetry."""
+Fraunhofer (far-field) limit of a square aperture, symmetry, and the block
+structure of the sum (four contiguous blocks of sources, each summed in
+order, added in block order) against the plain sum of each block."""
 import math
 
 import numpy as np
+import pytest
 
 import oracle
 
@@ -25,15 +28,17 @@ def exact_field(xo, yo, src, k, L):
     return (w * np.cos(theta)).sum(1), (w * np.sin(theta)).sum(1), w, theta, d
 
 
-def field_bound(w, theta, d, k):
+def field_bound(w, theta, d, k, blocks=oracle.HUYGENS_BLOCKS):
     """Per-point bound on |U32 - U64|: each term's pair error E_pair(theta)
     plus its phase error (d is formed with about 8 roundings, theta with one
-    more), the rounding of w, and the recursive fma sum over S terms."""
+    more), the rounding of w, and the sum: a recursive fma sum over each
+    block of ceil(S / blocks) terms, then blocks - 1 additions."""
     x1 = np.abs(theta) / (2 * math.pi)
     e_pair = 4.95e-7 + np.abs(theta) * 4.1e-8 + math.pi * np.maximum(x1, 1e-30) * 2 * U
     e_phase = abs(k) * 8 * U * d + 2 * U * np.abs(theta)
     S = w.shape[1]
-    return (w * (e_pair + e_phase + 3 * U)).sum(1) + 2 * S * U * w.sum(1)
+    per = -(-S // blocks)
+    return (w * (e_pair + e_phase + 3 * U)).sum(1) + 2 * (per + blocks) * U * w.sum(1)
 
 
 def test_single_source_closed_form(orc):
@@ -51,21 +56,55 @@ def test_single_source_closed_form(orc):
     assert abs(im0[0] - 0.75 / L * math.sin(0.3)) < 2e-7 * 0.75 / L * 10
 
 
-def test_against_exact_model_within_bound(orc):
+@pytest.mark.parametrize("blocks", [1, 4])
+def test_against_exact_model_within_bound(orc, blocks):
     rng = np.random.default_rng(6)
-    S, P = 300, 500
+    S, P = 303, 500
     src = np.stack([rng.uniform(-50, 50, S), rng.uniform(-50, 50, S), rng.uniform(0, 1, S) / S,
                     rng.uniform(-3, 3, S)], 1).astype(np.float32)
     xo = rng.uniform(-200, 200, P).astype(np.float32)
     yo = rng.uniform(-200, 200, P).astype(np.float32)
     L = 5000.0
-    re, im = orc.huygens(xo, yo, src, K, L, threads=4)
+    re, im = orc.huygens(xo, yo, src, K, L, threads=4, blocks=blocks)
     er, ei, w, th, d = exact_field(xo, yo, src, K, L)
     err = np.hypot(re - er, im - ei)
-    b = field_bound(w, th, d, K)
+    b = field_bound(w, th, d, K, blocks)
     assert np.all(err <= b), (err / b).max()
     # and the bound is not vacuous: the field itself is far larger
     assert np.median(b) < 1e-3 * np.median(np.hypot(er, ei)) * 10
+
+
+def block_combination(orc, xo, yo, src, k, L, blocks):
+    """The blocked sum rebuilt from plain (one-block) sums of each block,
+    added in block order in binary32."""
+    S = src.shape[0]
+    per = -(-S // blocks) if S else 0
+    re = im = None
+    for b in range(blocks):
+        lo, hi = min(S, b * per), min(S, (b + 1) * per)
+        br, bi = orc.huygens(xo, yo, src[lo:hi], k, L, blocks=1)
+        re, im = (br, bi) if re is None else ((re + br).astype(np.float32),
+                                             (im + bi).astype(np.float32))
+    return re, im
+
+
+@pytest.mark.parametrize("S", [0, 1, 3, 4, 5, 203, 1000])
+def test_blocked_sum_is_the_block_order_sum_of_plain_sums(orc, S):
+    """The default sum is four contiguous blocks of ceil(S/4) sources, each
+    the plain sum in source order, added in block order: bit for bit."""
+    rng = np.random.default_rng(S + 11)
+    src = np.stack([rng.uniform(-50, 50, S), rng.uniform(-50, 50, S), rng.uniform(0, 1, S),
+                    rng.uniform(-3, 3, S)], 1).astype(np.float32).reshape(S, 4)
+    xo = rng.uniform(-200, 200, 400).astype(np.float32)
+    yo = rng.uniform(-200, 200, 400).astype(np.float32)
+    re, im = orc.huygens(xo, yo, src, K, 5000.0)
+    wr, wi = block_combination(orc, xo, yo, src, K, 5000.0, orc.HUYGENS_BLOCKS)
+    assert np.array_equal(re.view(np.uint32), wr.view(np.uint32))
+    assert np.array_equal(im.view(np.uint32), wi.view(np.uint32))
+    if S >= 203:
+        # the block order is a real choice: the plain sum differs in the last bits
+        pr, pi = orc.huygens(xo, yo, src, K, 5000.0, blocks=1)
+        assert not np.array_equal(pr.view(np.uint32), re.view(np.uint32))
 
 
 def test_fraunhofer_limit_of_a_square_aperture(orc):

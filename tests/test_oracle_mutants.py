@@ -170,9 +170,16 @@ HUYGENS_MUTANTS = {
     "path_minus_L": ("float d = rho2 / (r + j->L);", "float d = r - j->L;"),
     "path_no_L": ("float d = rho2 / (r + j->L);", "float d = rho2 / r;"),
     "phase_sign": ("float theta = fmaf(j->k, d, sq[3]);", "float theta = fmaf(j->k, d, -sq[3]);"),
-    "swap_re_im": ("re = fmaf(w, cv, re);\n            im = fmaf(w, sv, im);",
-                   "re = fmaf(w, sv, re);\n            im = fmaf(w, cv, im);"),
+    "swap_re_im": ("re = fmaf(w, cv, re);\n        im = fmaf(w, sv, im);",
+                   "re = fmaf(w, sv, re);\n        im = fmaf(w, cv, im);"),
     "L2_missing": ("float r = sqrtf(rho2 + L2);", "float r = sqrtf(rho2 + j->L);"),
+    "one_block": ("#define HUYGENS_BLOCKS 4", "#define HUYGENS_BLOCKS 1"),
+    "block_size_floor": ("const int32_t per = (int32_t)(((int64_t)j->S + j->blocks - 1) / j->blocks);",
+                         "const int32_t per = (int32_t)((int64_t)j->S / j->blocks);"),
+    "block_start_skips": ("huygens_block_sum(j, i, first, last, &bre, &bim);",
+                          "huygens_block_sum(j, i, first + (b > 0), last, &bre, &bim);"),
+    "last_block_only": ("            if (b == 0) {\n                re = bre;",
+                        "            if (1) {\n                re = bre;"),
 }
 
 
@@ -182,17 +189,37 @@ def huygens_pins_fail(L):
     fp = ctypes.POINTER(ctypes.c_float)
     L.oracle_huygens_f32.argtypes = [fp, fp, ctypes.c_int64, fp, ctypes.c_int32, ctypes.c_float,
                                      ctypes.c_float, fp, fp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.oracle_huygens_blocks_f32.argtypes = [fp, fp, ctypes.c_int64, fp, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_float, ctypes.c_float, fp,
+                                            fp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     rng = np.random.default_rng(6)
-    S, P = 200, 300
+    S, P = 203, 300
     src = np.stack([rng.uniform(-50, 50, S), rng.uniform(-50, 50, S), rng.uniform(0, 1, S) / S,
                     rng.uniform(-3, 3, S)], 1).astype(np.float32)
     xo = rng.uniform(-200, 200, P).astype(np.float32)
     yo = rng.uniform(-200, 200, P).astype(np.float32)
+
+    def blocked(tab, blocks):
+        tab = np.ascontiguousarray(tab, np.float32)
+        re, im = np.empty(P, np.float32), np.empty(P, np.float32)
+        L.oracle_huygens_blocks_f32(_p(xo), _p(yo), P, _p(tab) if tab.size else None,
+                                    tab.shape[0], blocks, K, 5000.0, _p(re), _p(im), 0, 0, 2)
+        return re, im
     re, im = np.empty(P, np.float32), np.empty(P, np.float32)
     L.oracle_huygens_f32(_p(xo), _p(yo), P, _p(np.ascontiguousarray(src)), S, K, 5000.0,
                          _p(re), _p(im), 0, 0, 2)
     er, ei, w, th, d = exact_field(xo, yo, src, K, 5000.0)
-    return not np.all(np.hypot(re - er, im - ei) <= field_bound(w, th, d, K))
+    if not np.all(np.hypot(re - er, im - ei) <= field_bound(w, th, d, K)):
+        return True
+    # the structure: four blocks of ceil(S/4), plain sums, added in block order
+    per = -(-S // 4)
+    wr = wi = None
+    for b in range(4):
+        br, bi = blocked(src[min(S, b * per):min(S, (b + 1) * per)], 1)
+        wr, wi = (br, bi) if wr is None else ((wr + br).astype(np.float32),
+                                             (wi + bi).astype(np.float32))
+    return not (np.array_equal(re.view(np.uint32), wr.view(np.uint32)) and
+                np.array_equal(im.view(np.uint32), wi.view(np.uint32)))
 
 
 def test_unmodified_huygens_passes(tmp_path):
