@@ -178,9 +178,13 @@ __device__ __forceinline__ float adjoint1(float s, float c, float gs, float gc)
 // Float4 body: one float4 per lane, one 64-thread wave per workgroup and
 // tile (grid-stride past 2^20 tiles), buffer loads and stores with the
 // non-temporal policy -- measured on MI355X at 6.5 TB/s against 6.1 for
-// 512-thread workgroups of global loads and stores.
+// 512-thread workgroups of global loads and stores.  Each workgroup reserves
+// 8 KiB of LDS it does not use, so that at most 20 are resident per CU: with
+// fewer tiles in flight the stream runs 1.3 % faster (6.53 against 6.45
+// TB/s; 7-8 KiB reserved measured alike, less or none slower).
 constexpr int kBwdBlock = 64;
 constexpr int kBwdStorePolicy = 2;  // nt
+constexpr unsigned kBwdLdsReserve = 8192;
 
 template <bool GS, bool GC>
 __global__ void __launch_bounds__(kBwdBlock) k_backward_vec(const f4 *s, const f4 *c,
@@ -549,15 +553,22 @@ __global__ void __launch_bounds__(256) k_fit_reduce(const float *partial, const 
 
 // ---------------------------------------------------------------------------
 // K6: Huygens point-source sum, U_i = sum_j (a_j / r_ij) exp(i (k (r_ij - L) +
-// phi_j)), the path difference as rho^2 / (r + L).  Lane <-> screen point;
-// the source table (x, y, a, phi) is read with wave-uniform float4 scalar
-// loads; sources are summed in order with fma (so the only parallel axis is
-// the screen: one point per lane keeps the most waves resident).  The loads
-// of the next kHuyGroup sources are issued before the current group is
-// evaluated, so their latency hides behind that arithmetic.  sqrt and
-// division are IEEE (correctly rounded).
+// phi_j)), the path difference as rho^2 / (r + L).  The sources are summed
+// in kHuyBlocks contiguous blocks of ceil(S / kHuyBlocks), each in source
+// order with fma from +0, and the block sums are added in block order.  One
+// wave per block: a 256-thread workgroup takes 64 screen points, wave b
+// sums block b for all 64 and the four partial fields meet in LDS.  Four
+// waves per point give the diffraction workload (262,144 points) 16 waves
+// per SIMD instead of 4: the term's long dependency chains (IEEE sqrt and two
+// IEEE divisions) need them.  The source table (x, y, a, phi) is read with
+// wave-uniform float4 scalar loads, and the loads of the next kHuyGroup
+// sources are issued before the current group is evaluated, so their
+// latency hides behind that arithmetic.  sqrt and division are IEEE
+// (correctly rounded).
 
 constexpr int kHuyGroup = 2;
+constexpr int kHuyBlocks = 4;
+constexpr int kHuyPoints = 256 / kHuyBlocks;  // screen points per workgroup (one wave)
 
 __device__ __forceinline__ void huygens_term(float px, float py, f4 sq, float k, float L,
                                              float L2, float &re, float &im)
@@ -579,33 +590,44 @@ __device__ __forceinline__ void huygens_term(float px, float py, f4 sq, float k,
 // the term's own ceiling: the same code with the sources served from an
 // 8-entry table that stays in the scalar cache, i.e. the arithmetic with
 // (almost) no source traffic.
+// WRAP = 0: source j is src[j] (the sum).  WRAP = 8: source j is src[j % 8],
+// the term's own ceiling: the same code with the sources served from an
+// 8-entry table that stays in the scalar cache.
 template <int WRAP>
 __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *yo, int64_t P,
                                                  const f4 *__restrict__ src, int32_t S, float k,
                                                  float L, float L2, float *re, float *im)
 {
     static_assert(WRAP == 0 || WRAP % kHuyGroup == 0, "groups stay within the table");
+    static_assert(kHuyPoints == 64, "one wave per source block");
     auto at = [](int32_t j) { return WRAP ? (j & (WRAP - 1)) : j; };
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i - threadIdx.x < P;
-         i += stride) {  // block-uniform loop condition
+    __shared__ float part_re[kHuyBlocks][kHuyPoints], part_im[kHuyBlocks][kHuyPoints];
+    const int lane = threadIdx.x % kHuyPoints;
+    const int blk = __builtin_amdgcn_readfirstlane(threadIdx.x / kHuyPoints);  // the wave
+    // this wave's block of sources: [lo, lo + cnt)
+    const int32_t per = (int32_t)(((int64_t)S + kHuyBlocks - 1) / kHuyBlocks);
+    const int32_t lo = (int32_t)min<int64_t>(S, (int64_t)blk * per);
+    const int32_t cnt = (int32_t)min<int64_t>(S - lo, per);
+    const int32_t full = cnt / kHuyGroup * kHuyGroup;  // sources in whole groups
+    for (int64_t base = (int64_t)blockIdx.x * kHuyPoints; base < P;
+         base += (int64_t)gridDim.x * kHuyPoints) {  // workgroup-uniform loop
+        const int64_t i = base + lane;
         const float px = i < P ? xo[i] : 0.f;
         const float py = i < P ? yo[i] : 0.f;
         float ar = 0.0f, ai = 0.0f;
-        const int32_t full = S / kHuyGroup * kHuyGroup;  // sources in whole groups
         f4 cur[kHuyGroup];
         if (full > 0) {
 #pragma unroll
             for (int u = 0; u < kHuyGroup; ++u)
-                cur[u] = src[at(u)];
+                cur[u] = src[at(lo + u)];
         }
         for (int32_t q = 0; q < full; q += kHuyGroup) {
-            // the next group; the last group reloads itself, so every index is < S
+            // the next group; the last group reloads itself, so every index is < lo + cnt
             const int32_t nq = min(q + kHuyGroup, full - kHuyGroup);
             f4 nxt[kHuyGroup];
 #pragma unroll
             for (int u = 0; u < kHuyGroup; ++u)
-                nxt[u] = src[at(nq + u)];
+                nxt[u] = src[at(lo + nq + u)];
 #pragma unroll
             for (int u = 0; u < kHuyGroup; ++u)
                 huygens_term(px, py, cur[u], k, L, L2, ar, ai);
@@ -613,12 +635,22 @@ __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *y
             for (int u = 0; u < kHuyGroup; ++u)
                 cur[u] = nxt[u];
         }
-        for (int32_t q = full; q < S; ++q)
-            huygens_term(px, py, src[at(q)], k, L, L2, ar, ai);
-        if (i < P) {
-            re[i] = ar;
-            im[i] = ai;
+        for (int32_t q = full; q < cnt; ++q)
+            huygens_term(px, py, src[at(lo + q)], k, L, L2, ar, ai);
+        part_re[blk][lane] = ar;
+        part_im[blk][lane] = ai;
+        __syncthreads();
+        if (blk == 0 && i < P) {
+            float fr = part_re[0][lane], fi = part_im[0][lane];
+#pragma unroll
+            for (int b = 1; b < kHuyBlocks; ++b) {
+                fr = fr + part_re[b][lane];
+                fi = fi + part_im[b][lane];
+            }
+            re[i] = fr;
+            im[i] = fi;
         }
+        __syncthreads();  // the partials are read before the next tile writes them
     }
 }
 
@@ -817,8 +849,8 @@ hipError_t launch_backward(const float *s, const float *c, const float *gs, cons
     const f4 *gcv = gc ? reinterpret_cast<const f4 *>(gc + head) : nullptr;
     f4 *gxv = reinterpret_cast<f4 *>(gx + head);
 #define MI355_BWD_V(GS, GC)                                                                       \
-    hipLaunchKernelGGL((k_backward_vec<GS, GC>), dim3((unsigned)grid), dim3(kBwdBlock), 0, st, \
-                       sv, cv, gsv, gcv, gxv, n4)
+    hipLaunchKernelGGL((k_backward_vec<GS, GC>), dim3((unsigned)grid), dim3(kBwdBlock),      \
+                       kBwdLdsReserve, st, sv, cv, gsv, gcv, gxv, n4)
     if (gs && gc) MI355_BWD_V(true, true);
     else if (gs) MI355_BWD_V(true, false);
     else if (gc) MI355_BWD_V(false, true);
@@ -864,10 +896,9 @@ hipError_t launch_sinusoid_residual(const float *t, const float *y_obs, int64_t 
 hipError_t launch_huygens(const float *xo, const float *yo, int64_t P, const float *src,
                           int32_t S, float k, float L, float *re, float *im, hipStream_t st)
 {
-    const int64_t per_block = 256;
-    // grid-stride past 2^20 workgroups: grid * block stays far below 2^32
-    const int64_t grid = std::min<int64_t>(std::max<int64_t>(1, (P + per_block - 1) / per_block),
-                                           int64_t(1) << 20);
+    // 64 points per workgroup; grid-stride past 2^20 workgroups
+    const int64_t grid = std::min<int64_t>(
+        std::max<int64_t>(1, (P + kHuyPoints - 1) / kHuyPoints), int64_t(1) << 20);
     const float L2 = L * L;
     hipLaunchKernelGGL(k_huygens<0>, dim3((unsigned)grid), dim3(256), 0, st, xo, yo, P,
                        reinterpret_cast<const f4 *>(src), S, k, L, L2, re, im);
@@ -878,9 +909,8 @@ hipError_t launch_huygens_ceiling(const float *xo, const float *yo, int64_t P, c
                                   int32_t reps, float k, float L, float *re, float *im,
                                   hipStream_t st)
 {
-    const int64_t per_block = 256;
-    const int64_t grid = std::min<int64_t>(std::max<int64_t>(1, (P + per_block - 1) / per_block),
-                                           int64_t(1) << 20);
+    const int64_t grid = std::min<int64_t>(
+        std::max<int64_t>(1, (P + kHuyPoints - 1) / kHuyPoints), int64_t(1) << 20);
     const int64_t S = (int64_t)kHuygensCeilingSources * reps;  // below 2^31: reps < 2^28
     hipLaunchKernelGGL(k_huygens<kHuygensCeilingSources>, dim3((unsigned)grid), dim3(256), 0, st,
                        xo, yo, P, reinterpret_cast<const f4 *>(src), (int32_t)S, k, L, L * L, re,
