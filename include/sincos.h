@@ -328,8 +328,9 @@ SINCOS_API int sincos_copy_ceiling_f32(const float *x, float *s, float *c, int64
  *                            tiles read once into LDS: wave 0 stores the
  *                            tile to s, wave 1 to c.
  *   SINCOS_PROBE_COPY_XCD    s = c = x in the plain schedule with unroll 1,
- *                            the tiles dealt so that each of the 8 XCDs
- *                            sweeps a contiguous eighth of the array.
+ *                            the tiles dealt to the 8 XCDs in runs of
+ *                            launch->grid consecutive tiles (1 = the plain
+ *                            order; 0 = a contiguous eighth per XCD).
  * policy: -1 = the plain kernel's (loads non-temporal, stores sc1); for
  * READ, WRITE, WRITE1 and COPY also the cache-policy bits of the stores (of
  * the loads for READ): 0, 1 (sc0), 2 (nt), 16 (sc1), 17 (sc0|sc1) or 18

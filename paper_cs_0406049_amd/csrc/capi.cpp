@@ -549,7 +549,8 @@ extern "C" int sincos_stream_probe_f32(int32_t probe, int32_t policy, const floa
     LaunchShape sh;
     if ((rc = check_shape(launch, kFormPlain, &sh)) != SINCOS_OK)
         return rc;
-    if (probe == kProbeCopyXcd && (n / 4 + sh.block - 1) / sh.block + 8 > (int64_t(1) << 24))
+    // the XCD schedule launches up to twice the tiles: keep grid * block below 2^32
+    if (probe == kProbeCopyXcd && n / 4 > (int64_t(1) << 30))
         return set_error(SINCOS_EINVAL, std::string(who) + ": n too large for the XCD schedule");
     if (n == 0)
         return SINCOS_OK;

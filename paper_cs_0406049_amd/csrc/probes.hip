@@ -153,14 +153,17 @@ __global__ void __launch_bounds__(128) k_probe_copy_lds(const f4 *x, f4 *s, f4 *
 }
 
 // 1-read / 2-write, the plain kernel's tile, with workgroups mapped to tiles
-// so that each of the 8 XCDs (which take workgroups round-robin) sweeps its
-// own contiguous eighth of the array.  One tile per workgroup: the grid is
-// 8 * ceil(tiles / 8); workgroups past the last tile do nothing.
+// so that each of the 8 XCDs (which take workgroups round-robin) takes runs
+// of `run` consecutive tiles: XCD x gets tiles x*run .. x*run + run - 1 of
+// every 8*run.  run = 1 is the plain order; run = ceil(tiles / 8) gives each
+// XCD a contiguous eighth of the array.  One tile per workgroup; workgroups
+// past the last tile do nothing.
 __global__ void __launch_bounds__(1024) k_probe_copy_xcd(const f4 *x, f4 *s, f4 *c, int64_t n4,
-                                                         int64_t per_xcd)
+                                                         int64_t run)
 {
     const int bd = blockDim.x;
-    const int64_t tile_idx = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int64_t k = blockIdx.x / 8;  // this workgroup's index on its XCD
+    const int64_t tile_idx = (k / run) * 8 * run + (int64_t)(blockIdx.x % 8) * run + k % run;
     const int64_t t0 = tile_idx * bd;
     if (t0 >= n4)
         return;
@@ -290,9 +293,10 @@ hipError_t launch_stream_probe(int probe, int policy, const float *x, float *s, 
     }
     case kProbeCopyXcd: {
         const int64_t tiles = (n4 + bd - 1) / bd;
-        const int64_t per_xcd = (tiles + 7) / 8;
-        hipLaunchKernelGGL(k_probe_copy_xcd, dim3((unsigned)(8 * per_xcd)), dim3(bd), lds, st, xv,
-                           sv, cv, n4, per_xcd);
+        const int64_t run = std::max<int64_t>(1, std::min<int64_t>(sh.grid, (tiles + 7) / 8));
+        const int64_t grid = (tiles + 8 * run - 1) / (8 * run) * 8 * run;
+        hipLaunchKernelGGL(k_probe_copy_xcd, dim3((unsigned)grid), dim3(bd), lds, st, xv, sv, cv,
+                           n4, run);
         break;
     }
     default:
