@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmi355_sincos.so")
 
 SOURCES = ["plain.hip", "forms.hip", "ablation.hip", "probes.hip", "capi.cpp", "serve.cpp", "tuning.cpp"]
-HEADERS = ["internal.hpp", "sincos_core.hpp", "stream.hpp", "serve.hpp"]
+HEADERS = ["internal.hpp", "sincos_core.hpp", "stream.hpp", "serve.hpp", "sqrt_rn.hpp"]
 
 # -ffp-contract=off: the SPLIT arithmetic must not be fused (FUSED uses
 # explicit fma builtins, CONTRACT re-enables contraction with a pragma).
@@ -49,6 +49,22 @@ def build(verbose: bool = False) -> str:
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB
+
+
+# GPU test helpers built beside the tests (not part of the library).
+TEST_HELPERS = [("tests/native/sqrt_rn_check.hip", "tests/native/libsqrt_rn_check.so")]
+
+
+def build_test_helpers(verbose: bool = False) -> None:
+    """Compile the GPU tests' helper libraries with the library's flags."""
+    for src, out in TEST_HELPERS:
+        out = os.path.join(ROOT, out)
+        tmp = out + ".tmp%d" % os.getpid()
+        cmd = [hipcc(), *HIPFLAGS, os.path.join(ROOT, src), "-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        os.replace(tmp, out)
 
 
 def is_built() -> bool:

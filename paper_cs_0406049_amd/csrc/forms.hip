@@ -2,6 +2,7 @@
 // interleaved-output, ragged, adjoint, sinusoid-model and Huygens kernels and
 // their launchers.  All arithmetic is binary32 VALU (sincos_core.hpp).
 #include "internal.hpp"
+#include "sqrt_rn.hpp"
 #include "stream.hpp"
 
 #include <algorithm>
@@ -570,6 +571,9 @@ constexpr int kHuyGroup = 2;
 constexpr int kHuyBlocks = 4;
 constexpr int kHuyPoints = 256 / kHuyBlocks;  // screen points per workgroup (one wave)
 
+// SQRT_RN: L^2 >= 2^-96, so rho^2 + L^2 is in the range where sqrt_rn is the
+// IEEE square root (7 fewer instructions than the general sequence).
+template <bool SQRT_RN>
 __device__ __forceinline__ void huygens_term(float px, float py, f4 sq, float k, float L,
                                              float L2, float &re, float &im)
 {
@@ -577,7 +581,7 @@ __device__ __forceinline__ void huygens_term(float px, float py, f4 sq, float k,
     const float dy = py - sq.y;
     const float dy2 = dy * dy;
     const float rho2 = __builtin_fmaf(dx, dx, dy2);
-    const float rr = __builtin_sqrtf(rho2 + L2);
+    const float rr = SQRT_RN ? sqrt_rn(rho2 + L2) : __builtin_sqrtf(rho2 + L2);
     const float d = rho2 / (rr + L);
     float sv, cv;
     sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(k, d, sq.w), sv, cv);
@@ -593,7 +597,7 @@ __device__ __forceinline__ void huygens_term(float px, float py, f4 sq, float k,
 // WRAP = 0: source j is src[j] (the sum).  WRAP = 8: source j is src[j % 8],
 // the term's own ceiling: the same code with the sources served from an
 // 8-entry table that stays in the scalar cache.
-template <int WRAP>
+template <int WRAP, bool SQRT_RN>
 __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *yo, int64_t P,
                                                  const f4 *__restrict__ src, int32_t S, float k,
                                                  float L, float L2, float *re, float *im)
@@ -630,13 +634,13 @@ __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *y
                 nxt[u] = src[at(lo + nq + u)];
 #pragma unroll
             for (int u = 0; u < kHuyGroup; ++u)
-                huygens_term(px, py, cur[u], k, L, L2, ar, ai);
+                huygens_term<SQRT_RN>(px, py, cur[u], k, L, L2, ar, ai);
 #pragma unroll
             for (int u = 0; u < kHuyGroup; ++u)
                 cur[u] = nxt[u];
         }
         for (int32_t q = full; q < cnt; ++q)
-            huygens_term(px, py, src[at(lo + q)], k, L, L2, ar, ai);
+            huygens_term<SQRT_RN>(px, py, src[at(lo + q)], k, L, L2, ar, ai);
         part_re[blk][lane] = ar;
         part_im[blk][lane] = ai;
         __syncthreads();
@@ -900,8 +904,12 @@ hipError_t launch_huygens(const float *xo, const float *yo, int64_t P, const flo
     const int64_t grid = std::min<int64_t>(
         std::max<int64_t>(1, (P + kHuyPoints - 1) / kHuyPoints), int64_t(1) << 20);
     const float L2 = L * L;
-    hipLaunchKernelGGL(k_huygens<0>, dim3((unsigned)grid), dim3(256), 0, st, xo, yo, P,
-                       reinterpret_cast<const f4 *>(src), S, k, L, L2, re, im);
+    if (L2 >= kSqrtRnMin)
+        hipLaunchKernelGGL((k_huygens<0, true>), dim3((unsigned)grid), dim3(256), 0, st, xo, yo,
+                           P, reinterpret_cast<const f4 *>(src), S, k, L, L2, re, im);
+    else
+        hipLaunchKernelGGL((k_huygens<0, false>), dim3((unsigned)grid), dim3(256), 0, st, xo, yo,
+                           P, reinterpret_cast<const f4 *>(src), S, k, L, L2, re, im);
     return hipGetLastError();
 }
 
@@ -912,9 +920,15 @@ hipError_t launch_huygens_ceiling(const float *xo, const float *yo, int64_t P, c
     const int64_t grid = std::min<int64_t>(
         std::max<int64_t>(1, (P + kHuyPoints - 1) / kHuyPoints), int64_t(1) << 20);
     const int64_t S = (int64_t)kHuygensCeilingSources * reps;  // below 2^31: reps < 2^28
-    hipLaunchKernelGGL(k_huygens<kHuygensCeilingSources>, dim3((unsigned)grid), dim3(256), 0, st,
-                       xo, yo, P, reinterpret_cast<const f4 *>(src), (int32_t)S, k, L, L * L, re,
-                       im);
+    const float L2 = L * L;
+    if (L2 >= kSqrtRnMin)
+        hipLaunchKernelGGL((k_huygens<kHuygensCeilingSources, true>), dim3((unsigned)grid),
+                           dim3(256), 0, st, xo, yo, P, reinterpret_cast<const f4 *>(src),
+                           (int32_t)S, k, L, L2, re, im);
+    else
+        hipLaunchKernelGGL((k_huygens<kHuygensCeilingSources, false>), dim3((unsigned)grid),
+                           dim3(256), 0, st, xo, yo, P, reinterpret_cast<const f4 *>(src),
+                           (int32_t)S, k, L, L2, re, im);
     return hipGetLastError();
 }
 

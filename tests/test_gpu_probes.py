@@ -49,7 +49,9 @@ def test_copy_schedules_copy(torch_dev, n):
              (P.PROBE_COPY_BATCH, (64, 2, 0, -1), -1), (P.PROBE_COPY_BATCH, (256, 8, 5, -1), -1),
              (P.PROBE_COPY_SPLIT, (64, 1, 0, -1), -1), (P.PROBE_COPY_SPLIT, (64, 1, 7, -1), -1),
              (P.PROBE_COPY_LDS, (64, 1, 0, -1), -1), (P.PROBE_COPY_LDS, (64, 1, 3, 16384), -1),
-             (P.PROBE_COPY_XCD, (64, 1, 0, -1), -1), (P.PROBE_COPY_XCD, (256, 1, 0, 8192), -1)]
+             (P.PROBE_COPY_XCD, (64, 1, 0, -1), -1), (P.PROBE_COPY_XCD, (256, 1, 0, 8192), -1),
+             (P.PROBE_COPY_XCD, (64, 1, 1, -1), -1), (P.PROBE_COPY_XCD, (64, 1, 2, -1), -1),
+             (P.PROBE_COPY_XCD, (64, 1, 7, 8192), -1)]
     for probe, shape, policy in cases:
         s[:n].fill_(float("nan"))
         c[:n].fill_(float("nan"))
