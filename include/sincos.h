@@ -500,10 +500,10 @@ SINCOS_API int sincos_server_destroy(sincos_server_t *srv);
  * sincos_f32_ragged(_ex), ragged plans and the server's batches take
  * "ragged" (the server's one-launch-per-request mode takes "plain").
  * json: a JSON object {"plain": {...}, "ragged": {...}}, each holding any of
- *       the integer fields "block", "unroll", "grid" with the meanings and
- *       limits of sincos_launch_t.  Forms and fields left out get the
- *       built-in defaults (plain 64, 1, 0; ragged 256, 1, 0), so NULL or
- *       "{}" restores them.
+ *       the integer fields "block", "unroll", "grid", "lds" with the
+ *       meanings and limits of sincos_launch_t.  Forms and fields left out
+ *       get the built-in defaults (plain 64, 1, 0, 7168; ragged 256, 1, 0,
+ *       0), so NULL or "{}" restores them.
  * Errors: EINVAL for text outside that form (unknown or repeated keys,
  * non-integers, whitespace or numbers JSON does not allow, trailing text)
  * or values out of range; the current shapes are then kept.

@@ -29,7 +29,7 @@ def test_example_compiles_and_links(tmp_path):
 
 
 @pytest.mark.gpu
-def test_example_runs_on_the_gpu():
-    exe = EXE if os.path.exists(EXE) else build_example()
+def test_example_runs_on_the_gpu(tmp_path):
+    exe = build_example(str(tmp_path / "abi_example"))   # never a build from an older header
     r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and "abi_example: ok" in r.stdout, (r.stdout, r.stderr[-2000:])
