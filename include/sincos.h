@@ -90,8 +90,9 @@ typedef enum {
  *         for the plain form, 256 for the ragged form.
  * unroll: float4 per thread per loop trip (1, 2, 4 or 8); built-in 1.
  * grid:   workgroups; built-in 0 = one per tile, covering the array once
- *         (grid-stride beyond 2^20 workgroups); for the ragged form one per
- *         unit of work, and a smaller grid makes the launch persistent.
+ *         (grid-stride beyond 2^30 workgroups or 2^32 work-items); for the
+ *         ragged form one per unit of work, and a smaller grid makes the
+ *         launch persistent.
  * lds:    bytes of LDS each workgroup reserves at launch (up to 65536),
  *         which caps how many workgroups a CU holds at once (a CU has
  *         160 KiB); -1 = reserve none.  Built-in: 7168 for the plain form

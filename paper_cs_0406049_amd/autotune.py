@@ -2,7 +2,9 @@
 
 For a ragged batch it times one plan per candidate (block, unroll, grid, lds) with
 HIP events (the kernel only, each candidate replayed a few times after a
-warm-up), keeps the fastest, and caches the choice in a JSON file keyed by
+warm-up), then re-times the fastest few in interleaved rounds (so that a slow
+spell of the GPU hits every finalist alike) and keeps the one with the lowest
+median.  The choice is cached in a JSON file keyed by
 device architecture, CU count and a bucket of the batch's size (segment count
 and total elements, each rounded to a power of two), so a later batch of a
 similar size reuses it without timing.
@@ -122,15 +124,21 @@ def install(form: str, shape) -> None:
     _capi.set_tuning(cur)
 
 
+FINALISTS = 6
+ROUNDS = 5
+
+
 def tune_ragged(segs, lens=None, arith: int = _capi.ARITH_FUSED,
                 method: int = _capi.METHOD_NORMALIZED, cache_path: str | None = DEFAULT_CACHE,
                 force: bool = False, reps: int = 5, verbose: bool = False,
-                install_default: bool = False):
+                install_default: bool = False, finalists: int = FINALISTS,
+                rounds: int = ROUNDS):
     """Best (block, unroll, grid, lds) for this batch (from the cache if present).
     The arrays' contents are overwritten with valid outputs while timing.
     With install_default, the choice also becomes the library's default for
     ragged calls (grid capped there to each call's units)."""
-    best, _ = _tune_ragged(segs, lens, arith, method, cache_path, force, reps, verbose)
+    best, _ = _tune_ragged(segs, lens, arith, method, cache_path, force, reps, verbose,
+                           finalists, rounds)
     if install_default:
         install("ragged", best)
     return best
@@ -138,13 +146,16 @@ def tune_ragged(segs, lens=None, arith: int = _capi.ARITH_FUSED,
 
 def tune_ragged_table(segs, lens=None, arith: int = _capi.ARITH_FUSED,
                       method: int = _capi.METHOD_NORMALIZED, reps: int = 5,
-                      verbose: bool = False):
-    """Time every candidate (no cache) and return (best, [(ms, shape), ...])
-    with the timings sorted fastest first."""
-    return _tune_ragged(segs, lens, arith, method, None, True, reps, verbose)
+                      verbose: bool = False, finalists: int = FINALISTS,
+                      rounds: int = ROUNDS):
+    """Time every candidate (no cache) and return (best, [(ms, shape), ...]):
+    the finalists first, fastest median first (their ms is that median), then
+    the other candidates fastest first (their ms is the single first pass)."""
+    return _tune_ragged(segs, lens, arith, method, None, True, reps, verbose, finalists, rounds)
 
 
-def _tune_ragged(segs, lens, arith, method, cache_path, force, reps, verbose):
+def _tune_ragged(segs, lens, arith, method, cache_path, force, reps, verbose, finalists=FINALISTS,
+                 rounds=ROUNDS):
     import torch
     props = torch.cuda.get_device_properties(torch.cuda.current_device())
     arch = getattr(props, "gcnArchName", "unknown").split(":")[0]
@@ -165,6 +176,24 @@ def _tune_ragged(segs, lens, arith, method, cache_path, force, reps, verbose):
         if verbose:
             print("autotune %-18s %.4f ms" % (shape, ms), flush=True)
     results.sort()
+    # second stage: the fastest few again, in interleaved rounds
+    k = max(1, min(finalists, len(results)))
+    plans = [(shape, _capi.RaggedPlan(segs, lens, arith, method, launch=shape))
+             for _, shape in results[:k]]
+    times = {shape: [] for shape, _ in plans}
+    try:
+        for r in range(max(1, rounds)):
+            for j in range(k):
+                shape, plan = plans[(j + r) % k]
+                times[shape].append(time_plan(torch, plan, reps))
+    finally:
+        for _, plan in plans:
+            plan.destroy()
+    final = sorted((sorted(v)[len(v) // 2], shape) for shape, v in times.items())
+    if verbose:
+        for ms, shape in final:
+            print("autotune finalist %-18s median %.4f ms" % (shape, ms), flush=True)
+    results = final + results[k:]
     best_ms, best = results[0]
     if cache_path:
         with _lock:
