@@ -84,7 +84,7 @@ LaunchShape resolve_plain_shape(const LaunchShape &req, int64_t, const DeviceInf
     // below 2^32 (the dispatch packet counts work-items in 32 bits); the
     // kernels grid-stride past that.  A grid-stride loop over two or more
     // tiles per workgroup runs slower per byte than one tile each (0.95x at
-    // 2^29 elements with the 2^20-workgroup cap this replaces).
+    // 2^29 elements with two tiles per workgroup).
     LaunchShape sh = req;
     const int64_t max_grid = std::min<int64_t>(int64_t(1) << 30,
                                                int64_t(UINT32_MAX) / std::max(sh.block, 1));

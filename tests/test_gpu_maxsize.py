@@ -1,9 +1,10 @@
-"""Arrays past 2^31 elements (8 GiB in, 16 GiB out): 64-bit indexing, the
-grid-stride loop past 2^20 workgroups and the per-tile buffer ranges, checked
-against the oracle on sampled outputs (the oracle computes each one alone):
-random indices, both ends, and the neighbourhoods of 2^31 and of every
-multiple of 2^28 elements (where the 2^20-workgroup grid wraps at 64 float4
-per workgroup)."""
+"""Arrays past 2^31 elements (8 GiB in, 16 GiB out): 64-bit indexing, one
+workgroup per tile (the default grid: 2^23 workgroups here) and, with a grid
+of 2^20 workgroups, the grid-stride loop, and the per-tile buffer ranges,
+checked against the oracle on sampled outputs (the oracle computes each one
+alone): random indices, both ends, and the neighbourhoods of 2^31 and of
+every multiple of 2^28 elements (where a 2^20-workgroup grid wraps at 64
+float4 per workgroup)."""
 import numpy as np
 import pytest
 
@@ -52,16 +53,19 @@ def check_sampled(torch, x, s, c, n, arith, what):
     return idx.size
 
 
-@pytest.mark.parametrize("arith", [0, 1])
-def test_plain_past_2_31(big, arith):
+@pytest.mark.parametrize("arith,grid", [(0, 0), (1, 0), (0, 1 << 20)])
+def test_plain_past_2_31(big, arith, grid):
     torch, x = big
     from paper_cs_0406049_amd import _capi
     s = torch.empty_like(x)
     c = torch.empty_like(x)
-    _capi.sincos_f32_ex(x, s, c, N_BIG, arith, 0)
+    s.fill_(float("nan"))
+    c.fill_(float("nan"))
+    _capi.sincos_f32_ex(x, s, c, N_BIG, arith, 0, launch=(64, 1, grid, 0) if grid else None)
     torch.cuda.synchronize()
-    k = check_sampled(torch, x, s, c, N_BIG, arith, "plain n=2^31+3 arith %d" % arith)
-    log("plain past 2^31 (arith %d): %d sampled outputs bit-exact" % (arith, k))
+    what = "plain n=2^31+3 arith %d grid %d" % (arith, grid)
+    k = check_sampled(torch, x, s, c, N_BIG, arith, what)
+    log("%s: %d sampled outputs bit-exact" % (what, k))
     del s, c
 
 
