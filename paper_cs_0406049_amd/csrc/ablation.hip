@@ -133,7 +133,7 @@ __device__ __forceinline__ void pair_doublings4(const float (&x)[4], const Doubl
 }
 
 // x, s, c 16-byte aligned: tiles of 64 float4 (one per workgroup, grid-
-// stride past 2^20 workgroups); the last n % 4 elements by the first lanes of
+// stride past max_grid workgroups); the last n % 4 elements by the first lanes of
 // workgroup 0.  Each element is read before its outputs are written by the
 // same lane, so x may be s or c.
 template <class Pair4>
@@ -195,7 +195,7 @@ constexpr int kAblBlock = 64;  // the plain kernel's shape
 dim3 abl_grid(int64_t n)
 {
     const int64_t tiles = ((n >> 2) + kAblBlock - 1) / kAblBlock;
-    return dim3((unsigned)std::min<int64_t>(std::max<int64_t>(tiles, 1), int64_t(1) << 20));
+    return dim3((unsigned)std::min<int64_t>(std::max<int64_t>(tiles, 1), max_grid(kAblBlock)));
 }
 
 template <Arith A, Method M>

@@ -106,12 +106,8 @@ LaunchShape resolve_ragged_shape(const LaunchShape &req, int64_t total_units,
     LaunchShape sh = req;
     // default: one workgroup per unit of work (measured faster than a
     // persistent grid); a requested grid is capped to the number of units
-    // at most 2^30 workgroups, and grid * block below 2^32 (the dispatch
-    // packet counts work-items in 32 bits); each workgroup then takes a
-    // contiguous run of units
-    const int64_t max_grid = std::min<int64_t>(int64_t(1) << 30,
-                                               int64_t(UINT32_MAX) / std::max(sh.block, 1));
-    const int64_t cap = std::min<int64_t>(std::max<int64_t>(total_units, 1), max_grid);
+    // and to max_grid; each workgroup then takes a contiguous run of units
+    const int64_t cap = std::min<int64_t>(std::max<int64_t>(total_units, 1), max_grid(sh.block));
     sh.grid = (int)(sh.grid <= 0 ? cap : std::min<int64_t>(sh.grid, cap));
     return sh;
 }

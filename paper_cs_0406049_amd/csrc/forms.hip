@@ -177,7 +177,7 @@ __device__ __forceinline__ float adjoint1(float s, float c, float gs, float gc)
 }
 
 // Float4 body: one float4 per lane, one 64-thread wave per workgroup and
-// tile (grid-stride past 2^20 tiles), buffer loads and stores with the
+// tile (grid-stride past max_grid tiles), buffer loads and stores with the
 // non-temporal policy -- measured on MI355X at 6.5 TB/s against 6.1 for
 // 512-thread workgroups of global loads and stores.  Each workgroup reserves
 // 8 KiB of LDS it does not use, so that at most 20 are resident per CU: with
@@ -753,8 +753,8 @@ hipError_t launch_sincos_interleaved(const float *x, float *out, int64_t n, int 
     const int64_t n4 = n / 4;
     if (n4 > 0) {
         const int per_block = 64 * kIntWaves;
-        // grid-stride past 2^20 workgroups: grid * block stays far below 2^32
-        const int64_t grid = std::min<int64_t>((n4 + per_block - 1) / per_block, int64_t(1) << 20);
+        // one tile per workgroup up to max_grid, grid-stride past it
+        const int64_t grid = std::min<int64_t>((n4 + per_block - 1) / per_block, max_grid(per_block));
         if (layout == 0)
             hipLaunchKernelGGL(k_sincos_interleaved<0>, dim3((unsigned)grid), dim3(per_block), 0,
                                st, reinterpret_cast<const f4 *>(x), reinterpret_cast<f4 *>(out), n4);
@@ -844,9 +844,9 @@ hipError_t launch_backward(const float *s, const float *c, const float *gs, cons
         return hipGetLastError();
     }
     scalar(0, head);
-    // one float4 per thread, one tile per workgroup (grid-stride past 2^20)
+    // one float4 per thread, one tile per workgroup (grid-stride past max_grid)
     const int64_t grid = std::max<int64_t>(
-        1, std::min<int64_t>((n4 + kBwdBlock - 1) / kBwdBlock, int64_t(1) << 20));
+        1, std::min<int64_t>((n4 + kBwdBlock - 1) / kBwdBlock, max_grid(kBwdBlock)));
     const f4 *sv = reinterpret_cast<const f4 *>(s + head);
     const f4 *cv = reinterpret_cast<const f4 *>(c + head);
     const f4 *gsv = gs ? reinterpret_cast<const f4 *>(gs + head) : nullptr;

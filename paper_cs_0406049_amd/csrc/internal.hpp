@@ -150,6 +150,15 @@ int64_t ragged_units(const RaggedDesc &d, const LaunchShape &shape);
 RaggedDesc make_desc(const float *x, float *s, float *c, int64_t n);
 
 // Default launch shapes (resolved against the device).
+// Most workgroups one launch of `block`-thread workgroups may have: 2^30,
+// and grid * block below 2^32 (the dispatch packet counts work-items in 32
+// bits).  The streaming kernels take one tile per workgroup up to this and
+// grid-stride past it.
+inline int64_t max_grid(int block)
+{
+    const int64_t by_items = int64_t(UINT32_MAX) / (block > 0 ? block : 1);
+    return by_items < (int64_t(1) << 30) ? by_items : (int64_t(1) << 30);
+}
 LaunchShape resolve_plain_shape(const LaunchShape &req, int64_t n, const DeviceInfo &dev);
 LaunchShape resolve_ragged_shape(const LaunchShape &req, int64_t total_units,
                                  const DeviceInfo &dev);

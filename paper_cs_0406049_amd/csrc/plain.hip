@@ -80,16 +80,14 @@ __global__ void __launch_bounds__(1024) k_copy_1r2w(const f4 *x, f4 *s, f4 *c, i
 
 LaunchShape resolve_plain_shape(const LaunchShape &req, int64_t, const DeviceInfo &)
 {
-    // default: one workgroup per tile, up to 2^30 workgroups and grid * block
-    // below 2^32 (the dispatch packet counts work-items in 32 bits); the
-    // kernels grid-stride past that.  A grid-stride loop over two or more
+    // default: one workgroup per tile, up to max_grid; the kernels
+    // grid-stride past that.  A grid-stride loop over two or more
     // tiles per workgroup runs slower per byte than one tile each (0.95x at
     // 2^29 elements with two tiles per workgroup).
     LaunchShape sh = req;
-    const int64_t max_grid = std::min<int64_t>(int64_t(1) << 30,
-                                               int64_t(UINT32_MAX) / std::max(sh.block, 1));
-    if (sh.grid <= 0 || sh.grid > max_grid)
-        sh.grid = (int)max_grid;
+    const int64_t cap = max_grid(sh.block);
+    if (sh.grid <= 0 || sh.grid > cap)
+        sh.grid = (int)cap;
     return sh;
 }
 
