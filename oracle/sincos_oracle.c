@@ -758,12 +758,14 @@ int oracle_sinusoid_adjoint_f64(const float *t, const float *g, int64_t N, const
  * amplitude a_j and phase phi_j,
  *     U_i = sum_j (a_j / r_ij) exp(i (k (r_ij - L) + phi_j)),
  * with the obliquity factor taken as 1 and the path difference r - L
- * written as rho^2 / (r + L) so that no cancellation occurs.  In binary32,
- * for one block of sources j = lo..hi-1 in order, accumulators from +0:
+ * written as rho^2 / (r + L) so that no cancellation occurs.  Both
+ * quotients, rho^2 / (r + L) and a / r, come from one reciprocal of
+ * r (r + L).  In binary32, each operation rounded, for one block of
+ * sources j = lo..hi-1 in order, accumulators from +0:
  *     dx = xo - xa;  dy = yo - ya;  rho2 = fmaf(dx, dx, dy * dy)
- *     r = sqrtf(rho2 + L2) with L2 = L * L;  d = rho2 / (r + L)
- *     theta = fmaf(k, d, phi);  (s, c) = the pair of theta
- *     w = a / r;  re = fmaf(w, c, re);  im = fmaf(w, s, im)
+ *     r = sqrtf(rho2 + L2) with L2 = L * L;  e = r + L;  g = 1 / (r * e)
+ *     d = (rho2 * r) * g;  theta = fmaf(k, d, phi);  (s, c) = the pair of theta
+ *     w = (a * e) * g;  re = fmaf(w, c, re);  im = fmaf(w, s, im)
  * The sum over all S sources splits them into `blocks` contiguous blocks of
  * ceil(S / blocks) sources (the last ones shorter or empty), sums each block
  * as above and adds the block sums in block order, (((B0 + B1) + B2) + ...),
@@ -793,11 +795,13 @@ static void huygens_block_sum(const struct huygens_job *j, int64_t i, int32_t lo
         float dy2 = dy * dy;
         float rho2 = fmaf(dx, dx, dy2);
         float r = sqrtf(rho2 + L2);
-        float d = rho2 / (r + j->L);
+        float e = r + j->L;
+        float g = 1.0f / (r * e);
+        float d = (rho2 * r) * g;
         float theta = fmaf(j->k, d, sq[3]);
         float sv, cv;
         oracle_sincos_pair(theta, j->arith, j->method, &sv, &cv);
-        float w = sq[2] / r;
+        float w = (sq[2] * e) * g;
         re = fmaf(w, cv, re);
         im = fmaf(w, sv, im);
     }

@@ -30,15 +30,21 @@ def exact_field(xo, yo, src, k, L):
 
 def field_bound(w, theta, d, k, blocks=oracle.HUYGENS_BLOCKS):
     """Per-point bound on |U32 - U64|: each term's pair error E_pair(theta)
-    plus its phase error (d is formed with about 8 roundings, theta with one
-    more), the rounding of w, and the sum: a recursive fma sum over each
-    block of ceil(S / blocks) terms, then blocks - 1 additions."""
+    plus its phase error, the error of its weight, and the sum: a recursive
+    fma sum over each block of ceil(S / blocks) terms, then blocks - 1
+    additions.  Relative errors to first order in U: rho^2 <= 4U (dx, dy,
+    dy^2, the fma); r <= 3U (the sum with L^2, the square root); e = r + L
+    <= 4U.  With g = 1/(r e) the same rounded r enters the numerator and the
+    denominator of d = (rho^2 r) g and cancels: d = rho^2 / e times four
+    roundings, <= 4U + 4U + 4U = 12U (14U used); theta adds one rounding of
+    itself.  w = (a e) g = a / r times four roundings, <= 3U + 4U = 7U (8U
+    used)."""
     x1 = np.abs(theta) / (2 * math.pi)
     e_pair = 4.95e-7 + np.abs(theta) * 4.1e-8 + math.pi * np.maximum(x1, 1e-30) * 2 * U
-    e_phase = abs(k) * 8 * U * d + 2 * U * np.abs(theta)
+    e_phase = abs(k) * 14 * U * d + 2 * U * np.abs(theta)
     S = w.shape[1]
     per = -(-S // blocks)
-    return (w * (e_pair + e_phase + 3 * U)).sum(1) + 2 * (per + blocks) * U * w.sum(1)
+    return (w * (e_pair + e_phase + 8 * U)).sum(1) + 2 * (per + blocks) * U * w.sum(1)
 
 
 def test_single_source_closed_form(orc):

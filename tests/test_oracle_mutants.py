@@ -165,10 +165,14 @@ def test_mutant_fails_a_pin(tmp_path, name):
 # The Huygens sum's pins catch plausible mistakes in it too.
 
 HUYGENS_MUTANTS = {
-    "amp_times_r": ("float w = sq[2] / r;", "float w = sq[2] * r;"),
+    "amp_times_r": ("float w = (sq[2] * e) * g;", "float w = sq[2] * r;"),
+    "weight_drops_e": ("float w = (sq[2] * e) * g;", "float w = sq[2] * g;"),
+    "path_drops_r": ("float d = (rho2 * r) * g;", "float d = rho2 * g;"),
+    "recip_drops_r": ("float g = 1.0f / (r * e);", "float g = 1.0f / e;"),
+    "recip_of_r_only": ("float g = 1.0f / (r * e);", "float g = 1.0f / (r * r);"),
     "drop_dy": ("float rho2 = fmaf(dx, dx, dy2);", "float rho2 = dx * dx; (void)dy2;"),
-    "path_minus_L": ("float d = rho2 / (r + j->L);", "float d = r - j->L;"),
-    "path_no_L": ("float d = rho2 / (r + j->L);", "float d = rho2 / r;"),
+    "path_minus_L": ("float d = (rho2 * r) * g;", "float d = r - j->L;"),
+    "path_no_L": ("float e = r + j->L;", "float e = r;"),
     "phase_sign": ("float theta = fmaf(j->k, d, sq[3]);", "float theta = fmaf(j->k, d, -sq[3]);"),
     "swap_re_im": ("re = fmaf(w, cv, re);\n        im = fmaf(w, sv, im);",
                    "re = fmaf(w, sv, re);\n        im = fmaf(w, cv, im);"),
