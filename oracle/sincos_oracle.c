@@ -75,6 +75,7 @@
  */
 #define _GNU_SOURCE
 #include <fenv.h>
+#include <float.h>
 #include <math.h>
 #include <pthread.h>
 #include <stdint.h>
@@ -760,12 +761,18 @@ int oracle_sinusoid_adjoint_f64(const float *t, const float *g, int64_t N, const
  * with the obliquity factor taken as 1 and the path difference r - L
  * written as rho^2 / (r + L) so that no cancellation occurs.  Both
  * quotients, rho^2 / (r + L) and a / r, come from one reciprocal of
- * r (r + L).  In binary32, each operation rounded, for one block of
- * sources j = lo..hi-1 in order, accumulators from +0:
+ * r (r + L) while that product is a normal binary32; outside that range
+ * (r beyond about 2^63 or below about 2^-63) each is its own division.
+ * In binary32, each operation rounded, for one block of sources
+ * j = lo..hi-1 in order, accumulators from +0:
  *     dx = xo - xa;  dy = yo - ya;  rho2 = fmaf(dx, dx, dy * dy)
- *     r = sqrtf(rho2 + L2) with L2 = L * L;  e = r + L;  g = 1 / (r * e)
- *     d = (rho2 * r) * g;  theta = fmaf(k, d, phi);  (s, c) = the pair of theta
- *     w = (a * e) * g;  re = fmaf(w, c, re);  im = fmaf(w, s, im)
+ *     r = sqrtf(rho2 + L2) with L2 = L * L;  e = r + L;  x = r * e
+ *     if FLT_MIN <= x <= FLT_MAX:  g = 1 / x;  d = rho2 * (r * g);  w = a * (e * g)
+ *     else:                        d = rho2 / e;  w = a / r
+ *     theta = fmaf(k, d, phi);  (s, c) = the pair of theta
+ *     re = fmaf(w, c, re);  im = fmaf(w, s, im)
+ * (r g is 1 / e and e g is 1 / r up to rounding, so no intermediate grows
+ * past the quotients themselves.)
  * The sum over all S sources splits them into `blocks` contiguous blocks of
  * ceil(S / blocks) sources (the last ones shorter or empty), sums each block
  * as above and adds the block sums in block order, (((B0 + B1) + B2) + ...),
@@ -796,12 +803,19 @@ static void huygens_block_sum(const struct huygens_job *j, int64_t i, int32_t lo
         float rho2 = fmaf(dx, dx, dy2);
         float r = sqrtf(rho2 + L2);
         float e = r + j->L;
-        float g = 1.0f / (r * e);
-        float d = (rho2 * r) * g;
+        float x = r * e;
+        float d, w;
+        if (x >= FLT_MIN && x <= FLT_MAX) {
+            float g = 1.0f / x;
+            d = rho2 * (r * g);
+            w = sq[2] * (e * g);
+        } else {
+            d = rho2 / e;
+            w = sq[2] / r;
+        }
         float theta = fmaf(j->k, d, sq[3]);
         float sv, cv;
         oracle_sincos_pair(theta, j->arith, j->method, &sv, &cv);
-        float w = (sq[2] * e) * g;
         re = fmaf(w, cv, re);
         im = fmaf(w, sv, im);
     }

@@ -35,10 +35,11 @@ def field_bound(w, theta, d, k, blocks=oracle.HUYGENS_BLOCKS):
     additions.  Relative errors to first order in U: rho^2 <= 4U (dx, dy,
     dy^2, the fma); r <= 3U (the sum with L^2, the square root); e = r + L
     <= 4U.  With g = 1/(r e) the same rounded r enters the numerator and the
-    denominator of d = (rho^2 r) g and cancels: d = rho^2 / e times four
+    denominator of d = rho^2 (r g) and cancels: d = rho^2 / e times four
     roundings, <= 4U + 4U + 4U = 12U (14U used); theta adds one rounding of
-    itself.  w = (a e) g = a / r times four roundings, <= 3U + 4U = 7U (8U
-    used)."""
+    itself.  w = a (e g) = a / r times four roundings, <= 3U + 4U = 7U (8U
+    used).  Where r e is not a normal binary32 the term divides twice
+    instead: d <= 4U + 4U + U = 9U, w <= 3U + U = 4U, inside the same bound."""
     x1 = np.abs(theta) / (2 * math.pi)
     e_pair = 4.95e-7 + np.abs(theta) * 4.1e-8 + math.pi * np.maximum(x1, 1e-30) * 2 * U
     e_phase = abs(k) * 14 * U * d + 2 * U * np.abs(theta)
@@ -78,6 +79,59 @@ def test_against_exact_model_within_bound(orc, blocks):
     assert np.all(err <= b), (err / b).max()
     # and the bound is not vacuous: the field itself is far larger
     assert np.median(b) < 1e-3 * np.median(np.hypot(er, ei)) * 10
+
+
+# Geometries at the ends of the range, lengths scaled by s and k by 1/s (the
+# field is scale-free), so that the phases stay moderate and the bound
+# measures accuracy: r near 2^50 (one reciprocal; multiplying rho^2 by r
+# before the reciprocal would overflow there), L = 2^-64 (r (r + L) below
+# the normal range: two divisions) and L = 1.6e19 (r (r + L) above it).
+EXTREME_CASES = {
+    "big_r": (2.0 ** 44, 2.0 ** 45, 2.0 ** 50, 2.0 ** 44),
+    "tiny_L": (2.0 ** -66, 2.0 ** -65, 2.0 ** -64, 2.0 ** -66),
+    "huge_L": (2.0 ** 57, 2.0 ** 58, 1.6e19, 2.0 ** 57),
+}
+
+
+def extreme_case(name, S=57, P=64):
+    """(xo, yo, src, k, L) for one of EXTREME_CASES: sources within +-src_half
+    and points within +-pt_half, k = 2 pi / s."""
+    src_half, pt_half, L, s = EXTREME_CASES[name]
+    rng = np.random.default_rng(len(name))
+    src = np.stack([rng.uniform(-1, 1, S) * src_half, rng.uniform(-1, 1, S) * src_half,
+                    rng.uniform(0, 1, S) / S, rng.uniform(-3, 3, S)], 1).astype(np.float32)
+    xo = (rng.uniform(-1, 1, P) * pt_half).astype(np.float32)
+    yo = (rng.uniform(-1, 1, P) * pt_half).astype(np.float32)
+    return xo, yo, src, float(np.float32(K / s)), L
+
+
+def shared_fraction(xo, yo, src, L):
+    """Fraction of terms for which r (r + L), formed in binary32 as the
+    oracle forms it, is a normal binary32 (the one-reciprocal branch)."""
+    f = np.float32
+    dx = (xo[:, None] - src[None, :, 0]).astype(f)
+    dy = (yo[:, None] - src[None, :, 1]).astype(f)
+    rho2 = (dx.astype(np.float64) ** 2 + (dy * dy).astype(f)).astype(f)
+    r = np.sqrt((rho2 + f(f(L) * f(L))).astype(f)).astype(f)
+    e = (r + f(L)).astype(f)
+    with np.errstate(over="ignore", under="ignore"):
+        x = (r.astype(np.float64) * e).astype(f)
+    return float(((x >= np.finfo(f).tiny) & (x <= np.finfo(f).max)).mean())
+
+
+@pytest.mark.parametrize("name,shared", [("big_r", 1.0), ("tiny_L", 0.0), ("huge_L", 0.0)])
+def test_extreme_geometries_within_bound(orc, name, shared):
+    """At both ends of the range the field stays finite and within the bound
+    of the exact model, in the branch the case is built for."""
+    xo, yo, src, k, L = extreme_case(name)
+    assert shared_fraction(xo, yo, src, L) == shared
+    re, im = orc.huygens(xo, yo, src, k, L, threads=4)
+    er, ei, w, th, d = exact_field(xo, yo, src, k, L)
+    b = field_bound(w, th, d, k)
+    err = np.hypot(re.astype(np.float64) - er, im.astype(np.float64) - ei)
+    assert np.all(np.isfinite(re)) and np.all(np.isfinite(im))
+    assert np.all(err <= b), (err / b).max()
+    assert np.median(b) < 1e-2 * np.median(np.hypot(er, ei))
 
 
 def block_combination(orc, xo, yo, src, k, L, blocks):

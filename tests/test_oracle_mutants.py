@@ -31,12 +31,16 @@ MUTANTS = {
                      "for (int k = 0; k <= n - 2; k++)\n        p = mul_add(x2, p, coef[k], arith);"),
     "doubling_plus": ("*c_out = mul_sub_from(s, s, cos_sq, arith);",
                       "*c_out = mul_add(s, s, cos_sq, arith);"),
-    "doubling_no_two": ("*s_out = 2.0f * sin_cos;", "*s_out = sin_cos;"),
+    "doubling_no_two": ("*c_out = mul_sub_from(s, s, cos_sq, arith);\n    float sin_cos = s * c;\n"
+                        "    *s_out = 2.0f * sin_cos;",
+                        "*c_out = mul_sub_from(s, s, cos_sq, arith);\n    float sin_cos = s * c;\n"
+                        "    *s_out = sin_cos;"),
     "rejected_doubling": ("*c_out = mul_sub_from(s, s, cos_sq, arith);",
                           "(void)cos_sq; *c_out = mul_sub_from(2.0f * s, s, 1.0f, arith);"),
     "one_doubling": ("oracle_double_angle(hs, hc, arith, &fs, &fc);      /* angle 2 pi x   */",
                      "fs = hs; fc = hc;"),
-    "no_fix": ("*s = fs * m;\n    *c = fc * m;", "(void)m;\n    *s = fs;\n    *c = fc;"),
+    "no_fix": ("/* angle 2 pi x   */\n    *s = fs * m;\n    *c = fc * m;",
+               "/* angle 2 pi x   */\n    (void)m;\n    *s = fs;\n    *c = fc;"),
     "fix_sign": ("return mul_sub_from(s, s, two_less_cos_sq, arith);",
                  "return mul_add(s, s, two_less_cos_sq, arith);"),
     "ties_away": ("float whole = rintf(turns);", "float whole = roundf(turns);"),
@@ -49,8 +53,9 @@ MUTANTS = {
     "flush_subnormal": ("float turns = theta * reduction_constant();",
                         "float turns = theta * reduction_constant();\n"
                         "    if (fabsf(turns) < 1.17549435e-38f) turns = 0.0f;"),
-    "fix_before_doubling": ("*s = fs * m;\n    *c = fc * m;",
-                            "oracle_double_angle(hs * m, hc * m, arith, s, c);"),
+    "fix_before_doubling": ("/* angle 2 pi x   */\n    *s = fs * m;\n    *c = fc * m;",
+                            "/* angle 2 pi x   */\n"
+                            "    oracle_double_angle(hs * m, hc * m, arith, s, c);"),
 }
 
 FLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-pthread"]
@@ -156,7 +161,7 @@ def test_unmodified_oracle_passes_every_pin(tmp_path):
 def test_mutant_fails_a_pin(tmp_path, name):
     src = open(SRC).read()
     old, new = MUTANTS[name]
-    assert old in src, "mutation site not found: " + name
+    assert src.count(old) == 1, "mutation site not found or not unique: " + name
     L = _build(tmp_path, name, src.replace(old, new, 1))
     assert failed_pins(L), "no pin caught mutant " + name
 
@@ -164,14 +169,19 @@ def test_mutant_fails_a_pin(tmp_path, name):
 # ---------------------------------------------------------------------------
 # The Huygens sum's pins catch plausible mistakes in it too.
 
+I12 = " " * 12  # the indentation of the term's branches: sites in code, not in comments
 HUYGENS_MUTANTS = {
-    "amp_times_r": ("float w = (sq[2] * e) * g;", "float w = sq[2] * r;"),
-    "weight_drops_e": ("float w = (sq[2] * e) * g;", "float w = sq[2] * g;"),
-    "path_drops_r": ("float d = (rho2 * r) * g;", "float d = rho2 * g;"),
-    "recip_drops_r": ("float g = 1.0f / (r * e);", "float g = 1.0f / e;"),
-    "recip_of_r_only": ("float g = 1.0f / (r * e);", "float g = 1.0f / (r * r);"),
+    "amp_times_r": (I12 + "w = sq[2] * (e * g);", I12 + "w = sq[2] * r;"),
+    "weight_drops_e": (I12 + "w = sq[2] * (e * g);", I12 + "w = sq[2] * g;"),
+    "path_drops_r": (I12 + "d = rho2 * (r * g);", I12 + "d = rho2 * g;"),
+    "path_overflowing_order": (I12 + "d = rho2 * (r * g);", I12 + "d = (rho2 * r) * g;"),
+    "recip_drops_r": ("float x = r * e;", "float x = e;"),
+    "recip_of_r_only": ("float x = r * e;", "float x = r * r;"),
+    "fallback_path_no_L": ("} else {\n" + I12 + "d = rho2 / e;",
+                           "} else {\n" + I12 + "d = rho2 / r;"),
+    "fallback_amp_times_r": (I12 + "w = sq[2] / r;", I12 + "w = sq[2] * r;"),
     "drop_dy": ("float rho2 = fmaf(dx, dx, dy2);", "float rho2 = dx * dx; (void)dy2;"),
-    "path_minus_L": ("float d = (rho2 * r) * g;", "float d = r - j->L;"),
+    "path_minus_L": (I12 + "d = rho2 * (r * g);", I12 + "d = r - j->L;"),
     "path_no_L": ("float e = r + j->L;", "float e = r;"),
     "phase_sign": ("float theta = fmaf(j->k, d, sq[3]);", "float theta = fmaf(j->k, d, -sq[3]);"),
     "swap_re_im": ("re = fmaf(w, cv, re);\n        im = fmaf(w, sv, im);",
@@ -189,7 +199,7 @@ HUYGENS_MUTANTS = {
 
 def huygens_pins_fail(L):
     import math
-    from test_oracle_huygens import K, exact_field, field_bound
+    from test_oracle_huygens import EXTREME_CASES, K, exact_field, extreme_case, field_bound
     fp = ctypes.POINTER(ctypes.c_float)
     L.oracle_huygens_f32.argtypes = [fp, fp, ctypes.c_int64, fp, ctypes.c_int32, ctypes.c_float,
                                      ctypes.c_float, fp, fp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
@@ -215,6 +225,17 @@ def huygens_pins_fail(L):
     er, ei, w, th, d = exact_field(xo, yo, src, K, 5000.0)
     if not np.all(np.hypot(re - er, im - ei) <= field_bound(w, th, d, K)):
         return True
+    # the ends of the range: one reciprocal with r near 2^50, two divisions
+    # where r (r + L) leaves the normal range
+    for name in sorted(EXTREME_CASES):
+        exo, eyo, esrc, ek, eL = extreme_case(name)
+        ere, eim = np.empty(exo.size, np.float32), np.empty(exo.size, np.float32)
+        L.oracle_huygens_f32(_p(exo), _p(eyo), exo.size, _p(np.ascontiguousarray(esrc)),
+                             esrc.shape[0], ek, eL, _p(ere), _p(eim), 0, 0, 2)
+        er, ei, w, th, d = exact_field(exo, eyo, esrc, ek, eL)
+        err = np.hypot(ere.astype(np.float64) - er, eim.astype(np.float64) - ei)
+        if not np.all(err <= field_bound(w, th, d, ek)):
+            return True
     # the structure: four blocks of ceil(S/4), plain sums, added in block order
     per = -(-S // 4)
     wr = wi = None
@@ -234,7 +255,7 @@ def test_unmodified_huygens_passes(tmp_path):
 def test_huygens_mutant_fails_a_pin(tmp_path, name):
     src = open(SRC).read()
     old, new = HUYGENS_MUTANTS[name]
-    assert old in src, "mutation site not found: " + name
+    assert src.count(old) == 1, "mutation site not found or not unique: " + name
     assert huygens_pins_fail(_build(tmp_path, name, src.replace(old, new, 1))), name
 
 
