@@ -277,13 +277,18 @@ SINCOS_API int sinusoid_f32_fit_step_noalloc(const float *t, const float *y_obs,
  * in the plane z = 0,
  *     U_i = sum_j (a_j / r_ij) exp(i (k (r_ij - L) + phi_j)),
  * r_ij the distance, obliquity factor 1, the path difference r - L formed
- * as rho^2 / (r + L) (rho the lateral distance).  In binary32: dx, dy by
- * subtraction, rho2 = fma(dx, dx, dy*dy), r = sqrt(rho2 + fl(L*L)),
- * d = rho2 / (r + L), theta = fma(k, d, phi_j), the pair of theta (FUSED,
- * NORMALIZED), w = a_j / r, re = fma(w, c, re), im = fma(w, s, im) over
- * j = 0..S-1 in order from +0; sqrt and division correctly rounded.
+ * as rho^2 / (r + L) (rho the lateral distance).  In binary32, each
+ * operation rounded: dx, dy by subtraction, rho2 = fma(dx, dx, dy*dy),
+ * r = sqrt(rho2 + fl(L*L)) correctly rounded, e = r + L, x = r*e; while x is
+ * a normal binary32 both quotients come from one correctly rounded
+ * reciprocal g = 1/x: d = rho2*(r*g), w = a_j*(e*g); otherwise d = rho2/e,
+ * w = a_j/r (correctly rounded divisions).  theta = fma(k, d, phi_j), the
+ * pair of theta (FUSED, NORMALIZED), re = fma(w, c, re), im = fma(w, s, im).
+ * The sources are summed in 4 contiguous blocks of ceil(S/4), each in
+ * source order from +0, and the block sums are added in block order.
  * xo, yo, re, im: [P] device arrays; src: [S][4] = (x, y, a, phi), device,
- * 16-byte aligned.  L > 0.  Outputs may not overlap any input.           */
+ * 16-byte aligned.  0 < L < 1e18 (else EINVAL).  Outputs may not overlap
+ * any input.                                                              */
 SINCOS_API int huygens_f32(const float *xo, const float *yo, int64_t P, const float *src,
                            int32_t S, float k, float L, float *re, float *im, void *stream);
 

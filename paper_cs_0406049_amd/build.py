@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmi355_sincos.so")
 
 SOURCES = ["plain.hip", "forms.hip", "ablation.hip", "probes.hip", "capi.cpp", "serve.cpp", "tuning.cpp"]
-HEADERS = ["internal.hpp", "sincos_core.hpp", "stream.hpp", "serve.hpp", "sqrt_rn.hpp"]
+HEADERS = ["internal.hpp", "sincos_core.hpp", "stream.hpp", "serve.hpp", "sqrt_rn.hpp", "rcp_rn.hpp"]
 
 # -ffp-contract=off: the SPLIT arithmetic must not be fused (FUSED uses
 # explicit fma builtins, CONTRACT re-enables contraction with a pragma).
@@ -52,7 +52,8 @@ def build(verbose: bool = False) -> str:
 
 
 # GPU test helpers built beside the tests (not part of the library).
-TEST_HELPERS = [("tests/native/sqrt_rn_check.hip", "tests/native/libsqrt_rn_check.so")]
+TEST_HELPERS = [("tests/native/sqrt_rn_check.hip", "tests/native/libsqrt_rn_check.so"),
+                ("tests/native/rcp_rn_check.hip", "tests/native/librcp_rn_check.so")]
 
 
 def build_test_helpers(verbose: bool = False) -> None:

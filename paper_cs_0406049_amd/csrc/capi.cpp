@@ -1120,7 +1120,7 @@ static int check_huygens(const float *xo, const float *yo, int64_t P, const floa
         (S > 0 && (reinterpret_cast<uintptr_t>(src) & 15)))
         return set_error(SINCOS_EINVAL, who + ": arrays must be 4-byte aligned, src 16-byte aligned");
     if (!(L > 0.0f) || !(L < 1e18f))
-        return set_error(SINCOS_EINVAL, who + ": L must be positive and finite");
+        return set_error(SINCOS_EINVAL, who + ": L must be in (0, 1e18)");
     if (ranges_overlap(re, P, im, P) || ranges_overlap(re, P, xo, P) ||
         ranges_overlap(re, P, yo, P) || ranges_overlap(im, P, xo, P) ||
         ranges_overlap(im, P, yo, P) ||

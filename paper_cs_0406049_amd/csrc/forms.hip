@@ -2,10 +2,12 @@
 // interleaved-output, ragged, adjoint, sinusoid-model and Huygens kernels and
 // their launchers.  All arithmetic is binary32 VALU (sincos_core.hpp).
 #include "internal.hpp"
+#include "rcp_rn.hpp"
 #include "sqrt_rn.hpp"
 #include "stream.hpp"
 
 #include <algorithm>
+#include <cfloat>
 #include <mutex>
 #include <type_traits>
 
@@ -554,53 +556,113 @@ __global__ void __launch_bounds__(256) k_fit_reduce(const float *partial, const 
 
 // ---------------------------------------------------------------------------
 // K6: Huygens point-source sum, U_i = sum_j (a_j / r_ij) exp(i (k (r_ij - L) +
-// phi_j)), the path difference as rho^2 / (r + L).  The sources are summed
-// in kHuyBlocks contiguous blocks of ceil(S / kHuyBlocks), each in source
-// order with fma from +0, and the block sums are added in block order.  One
-// wave per block: a 256-thread workgroup takes 64 screen points, wave b
-// sums block b for all 64 and the four partial fields meet in LDS.  Four
-// waves per point give the diffraction workload (262,144 points) 16 waves
-// per SIMD instead of 4: the term's long dependency chains (IEEE sqrt and two
-// IEEE divisions) need them.  The source table (x, y, a, phi) is read with
-// wave-uniform float4 scalar loads, and the loads of the next kHuyGroup
-// sources are issued before the current group is evaluated, so their
-// latency hides behind that arithmetic.  sqrt and division are IEEE
-// (correctly rounded).
+// phi_j)), the path difference as rho^2 / (r + L), both quotients from one
+// reciprocal: e = r + L, g = 1 / (r e), d = rho^2 (r g), w = a (e g), each
+// operation rounded (two divisions, d = rho^2 / e and w = a / r, where r e
+// is not a normal binary32).  The sources are summed in kHuyBlocks contiguous blocks
+// of ceil(S / kHuyBlocks), each in source order with fma from +0, and the
+// block sums are added in block order.  One wave per block: a 256-thread
+// workgroup takes 64 screen points, wave b sums block b for all 64 and the
+// four partial fields meet in LDS.  Four waves per point give the
+// diffraction workload (262,144 points) 16,384 waves instead of 4096, enough
+// to keep 8 resident on every SIMD: the term's long dependency chains need
+// them.  The source table (x, y, a, phi) is read with wave-uniform float4
+// scalar loads, and the loads of the next kHuyGroup sources are issued
+// before the current group is evaluated, so their latency hides behind
+// that arithmetic.  The square root and the reciprocal are correctly
+// rounded.
 
 constexpr int kHuyGroup = 2;
 constexpr int kHuyBlocks = 4;
 constexpr int kHuyPoints = 256 / kHuyBlocks;  // screen points per workgroup (one wave)
+// rcp_rn serves the reciprocal when every coordinate of the wave's points
+// and of the group's sources is below 2^60 in magnitude and 2^-48 <= L <
+// 2^60 (checked by the launcher): then rho^2 < 2^123, r < 2^62, r + L < 2^63
+// and 2^-96 <= r (r + L) < 2^125, inside rcp_rn's range.  Otherwise (huge,
+// infinite or NaN coordinates) the group takes the IEEE division.
+constexpr uint32_t kHuyCoordMaxBits = 0x5D800000u;  // 2^60
 
-// SQRT_RN: L^2 >= 2^-96, so rho^2 + L^2 is in the range where sqrt_rn is the
-// IEEE square root (7 fewer instructions than the general sequence).
-template <bool SQRT_RN>
-__device__ __forceinline__ void huygens_term(float px, float py, f4 sq, float k, float L,
-                                             float L2, float &re, float &im)
+__device__ __forceinline__ bool huy_coord_ok(float v)
 {
-    const float dx = px - sq.x;
-    const float dy = py - sq.y;
-    const float dy2 = dy * dy;
-    const float rho2 = __builtin_fmaf(dx, dx, dy2);
-    const float rr = SQRT_RN ? sqrt_rn(rho2 + L2) : __builtin_sqrtf(rho2 + L2);
-    const float d = rho2 / (rr + L);
-    float sv, cv;
-    sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(k, d, sq.w), sv, cv);
-    const float w = sq.z / rr;
-    re = __builtin_fmaf(w, cv, re);
-    im = __builtin_fmaf(w, sv, im);
+    return (__builtin_bit_cast(uint32_t, v) & 0x7FFFFFFFu) < kHuyCoordMaxBits;
+}
+
+// The terms of G sources for one screen point, added to (re, im) in source
+// order.  SQRT_RN: L^2 >= 2^-96, so rho^2 + L^2 is in the range where
+// sqrt_rn is the IEEE square root (7 fewer instructions than the general
+// sequence).  fast (wave-uniform): every r (r + L) is in rcp_rn's range (see
+// kHuyCoordMaxBits), so rcp_rn is the IEEE reciprocal and the one-reciprocal
+// form applies; otherwise, lane by lane, the IEEE reciprocal while r (r + L)
+// is a normal binary32 and two IEEE divisions where it is not.  One branch
+// per group around the quotients only: the rest of the arithmetic is shared.
+template <int G, bool SQRT_RN>
+__device__ __forceinline__ void huygens_terms(float px, float py, const f4 *sq, bool fast,
+                                              float k, float L, float L2, float &re, float &im)
+{
+    float rho2[G], rr[G], e[G], x[G], d[G], w[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+        const float dx = px - sq[u].x;
+        const float dy = py - sq[u].y;
+        const float dy2 = dy * dy;
+        rho2[u] = __builtin_fmaf(dx, dx, dy2);
+        rr[u] = SQRT_RN ? sqrt_rn(rho2[u] + L2) : __builtin_sqrtf(rho2[u] + L2);
+        e[u] = rr[u] + L;
+        x[u] = rr[u] * e[u];
+    }
+    if (fast) {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const float g = rcp_rn(x[u]);
+            d[u] = rho2[u] * (rr[u] * g);
+            w[u] = sq[u].z * (e[u] * g);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const bool normal = x[u] >= FLT_MIN && x[u] <= FLT_MAX;
+            const float g = 1.0f / x[u];
+            d[u] = normal ? rho2[u] * (rr[u] * g) : rho2[u] / e[u];
+            w[u] = normal ? sq[u].z * (e[u] * g) : sq[u].z / rr[u];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+        float sv, cv;
+        sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(k, d[u], sq[u].w), sv, cv);
+        re = __builtin_fmaf(w[u], cv, re);
+        im = __builtin_fmaf(w[u], sv, im);
+    }
+}
+
+// Whether every source coordinate of a group is below 2^60 in magnitude:
+// one comparison of the largest magnitude bit pattern, no branches (the
+// values are wave-uniform, so this stays on the scalar unit).  The elements
+// are copied to scalars first: __builtin_bit_cast applied to a vector
+// element reads the vector's first element with this compiler.
+template <int G>
+__device__ __forceinline__ bool huy_sources_ok(const f4 *sq)
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+        const float x = sq[u].x, y = sq[u].y;
+        m = max(m, __builtin_bit_cast(uint32_t, x) & 0x7FFFFFFFu);
+        m = max(m, __builtin_bit_cast(uint32_t, y) & 0x7FFFFFFFu);
+    }
+    return m < kHuyCoordMaxBits;
 }
 
 // WRAP = 0: source j is src[j] (the sum).  WRAP = 8: source j is src[j % 8],
 // the term's own ceiling: the same code with the sources served from an
 // 8-entry table that stays in the scalar cache, i.e. the arithmetic with
-// (almost) no source traffic.
-// WRAP = 0: source j is src[j] (the sum).  WRAP = 8: source j is src[j % 8],
-// the term's own ceiling: the same code with the sources served from an
-// 8-entry table that stays in the scalar cache.
+// (almost) no source traffic.  rcp_ok: the launcher's part of the rcp_rn
+// condition (2^-48 <= L < 2^60, with SQRT_RN).
 template <int WRAP, bool SQRT_RN>
 __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *yo, int64_t P,
                                                  const f4 *__restrict__ src, int32_t S, float k,
-                                                 float L, float L2, float *re, float *im)
+                                                 float L, float L2, int rcp_ok, float *re,
+                                                 float *im)
 {
     static_assert(WRAP == 0 || WRAP % kHuyGroup == 0, "groups stay within the table");
     static_assert(kHuyPoints == 64, "one wave per source block");
@@ -618,12 +680,18 @@ __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *y
         const int64_t i = base + lane;
         const float px = i < P ? xo[i] : 0.f;
         const float py = i < P ? yo[i] : 0.f;
+        // wave-uniform: rcp_rn is allowed for this wave's points
+        const bool pts_ok =
+            SQRT_RN && rcp_ok &&
+            __builtin_amdgcn_ballot_w64(!(huy_coord_ok(px) && huy_coord_ok(py))) == 0;
         float ar = 0.0f, ai = 0.0f;
         f4 cur[kHuyGroup];
+        bool fast = false;
         if (full > 0) {
 #pragma unroll
             for (int u = 0; u < kHuyGroup; ++u)
                 cur[u] = src[at(lo + u)];
+            fast = pts_ok & huy_sources_ok<kHuyGroup>(cur);
         }
         for (int32_t q = 0; q < full; q += kHuyGroup) {
             // the next group; the last group reloads itself, so every index is < lo + cnt
@@ -632,15 +700,18 @@ __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *y
 #pragma unroll
             for (int u = 0; u < kHuyGroup; ++u)
                 nxt[u] = src[at(lo + nq + u)];
-#pragma unroll
-            for (int u = 0; u < kHuyGroup; ++u)
-                huygens_term<SQRT_RN>(px, py, cur[u], k, L, L2, ar, ai);
+            huygens_terms<kHuyGroup, SQRT_RN>(px, py, cur, fast, k, L, L2, ar, ai);
+            // the next group's path, decided once its sources have arrived
+            fast = pts_ok & huy_sources_ok<kHuyGroup>(nxt);
 #pragma unroll
             for (int u = 0; u < kHuyGroup; ++u)
                 cur[u] = nxt[u];
         }
-        for (int32_t q = full; q < cnt; ++q)
-            huygens_term<SQRT_RN>(px, py, src[at(lo + q)], k, L, L2, ar, ai);
+        for (int32_t q = full; q < cnt; ++q) {
+            const f4 sq = src[at(lo + q)];
+            huygens_terms<1, SQRT_RN>(px, py, &sq, pts_ok & huy_sources_ok<1>(&sq), k, L, L2,
+                                      ar, ai);
+        }
         part_re[blk][lane] = ar;
         part_im[blk][lane] = ai;
         __syncthreads();
@@ -904,12 +975,13 @@ hipError_t launch_huygens(const float *xo, const float *yo, int64_t P, const flo
     const int64_t grid = std::min<int64_t>(
         std::max<int64_t>(1, (P + kHuyPoints - 1) / kHuyPoints), int64_t(1) << 20);
     const float L2 = L * L;
+    const int rcp_ok = L2 >= kSqrtRnMin && L < 0x1p60f;
     if (L2 >= kSqrtRnMin)
         hipLaunchKernelGGL((k_huygens<0, true>), dim3((unsigned)grid), dim3(256), 0, st, xo, yo,
-                           P, reinterpret_cast<const f4 *>(src), S, k, L, L2, re, im);
+                           P, reinterpret_cast<const f4 *>(src), S, k, L, L2, rcp_ok, re, im);
     else
         hipLaunchKernelGGL((k_huygens<0, false>), dim3((unsigned)grid), dim3(256), 0, st, xo, yo,
-                           P, reinterpret_cast<const f4 *>(src), S, k, L, L2, re, im);
+                           P, reinterpret_cast<const f4 *>(src), S, k, L, L2, 0, re, im);
     return hipGetLastError();
 }
 
@@ -921,14 +993,15 @@ hipError_t launch_huygens_ceiling(const float *xo, const float *yo, int64_t P, c
         std::max<int64_t>(1, (P + kHuyPoints - 1) / kHuyPoints), int64_t(1) << 20);
     const int64_t S = (int64_t)kHuygensCeilingSources * reps;  // below 2^31: reps < 2^28
     const float L2 = L * L;
+    const int rcp_ok = L2 >= kSqrtRnMin && L < 0x1p60f;
     if (L2 >= kSqrtRnMin)
         hipLaunchKernelGGL((k_huygens<kHuygensCeilingSources, true>), dim3((unsigned)grid),
                            dim3(256), 0, st, xo, yo, P, reinterpret_cast<const f4 *>(src),
-                           (int32_t)S, k, L, L2, re, im);
+                           (int32_t)S, k, L, L2, rcp_ok, re, im);
     else
         hipLaunchKernelGGL((k_huygens<kHuygensCeilingSources, false>), dim3((unsigned)grid),
                            dim3(256), 0, st, xo, yo, P, reinterpret_cast<const f4 *>(src),
-                           (int32_t)S, k, L, L2, re, im);
+                           (int32_t)S, k, L, L2, 0, re, im);
     return hipGetLastError();
 }
 

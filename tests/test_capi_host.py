@@ -34,16 +34,17 @@ def test_every_declared_symbol_is_exported(L):
     assert set(names) == set(_capi._SIGNATURES), "binding and header disagree"
 
 
-def test_sqrt_check_helper_is_built_and_exports_its_entry(L):
-    """The GPU tests' square-root check library (built beside the tests by
-    __graft_entry__.build()) exports its one entry point."""
+@pytest.mark.parametrize("name", ["sqrt_rn_check", "rcp_rn_check"])
+def test_check_helpers_are_built_and_export_their_entry(L, name):
+    """The GPU tests' square-root and reciprocal check libraries (built beside
+    the tests by __graft_entry__.build()) export their one entry point."""
     import subprocess
-    lib = os.path.join(ROOT, "tests", "native", "libsqrt_rn_check.so")
+    lib = os.path.join(ROOT, "tests", "native", "lib%s.so" % name)
     if not os.path.exists(lib):
         hipbuild.build_test_helpers()
     out = subprocess.run(["nm", "-D", "--defined-only", lib], capture_output=True,
                          text=True).stdout
-    assert re.search(r"\bT sqrt_rn_check$", out, re.M), out
+    assert re.search(r"\bT %s$" % name, out, re.M), out
 
 
 def test_only_declared_symbols_are_exported(L):

@@ -1,5 +1,8 @@
 """Huygens point-source sum on the GPU: bit-exact against the oracle (the
-binary32 sequence, sources summed in order, IEEE sqrt and division)."""
+binary32 sequence: four blocks of sources each summed in order, IEEE square
+root, both quotients from one IEEE reciprocal), on the fast paths
+(sqrt_rn, rcp_rn) and on the IEEE fallbacks the kernel takes for extreme
+screen distances and coordinates."""
 import math
 
 import numpy as np
@@ -73,6 +76,8 @@ def test_validation(torch_dev):
     with pytest.raises(_capi.SincosError):
         _capi.huygens_f32(x, x, src, 1.0, -1.0, out, out2)          # L <= 0
     with pytest.raises(_capi.SincosError):
+        _capi.huygens_f32(x, x, src, 1.0, 1e18, out, out2)          # L >= 1e18
+    with pytest.raises(_capi.SincosError):
         _capi.huygens_f32(x, x, src, 1.0, 10.0, out, out)           # re == im
     with pytest.raises(_capi.SincosError):
         _capi.huygens_f32(x, x, src[1:].data_ptr(), 1.0, 10.0, out, out2, 8, 3)  # src misaligned
@@ -102,3 +107,59 @@ def test_term_ceiling_is_the_sum_over_the_repeated_table(torch_dev, P, reps):
     assert_bit_exact(im.cpu().numpy(), io, "ceiling im P=%d reps=%d" % (P, reps))
     with pytest.raises(_capi.SincosError):
         _capi.huygens_term_ceiling_f32(xd, yd, sd, -1, p.k, p.L, re, im)
+
+
+def _mixed(rng, P, S, big, every_src, every_pt):
+    """Ordinary coordinates with every `every_src`-th source and every
+    `every_pt`-th screen point moved to +-big."""
+    src = np.stack([rng.uniform(-100, 100, S), rng.uniform(-100, 100, S), rng.uniform(0, 1, S) / S,
+                    rng.uniform(-math.pi, math.pi, S)], 1).astype(np.float32)
+    xo = rng.uniform(-300, 300, P).astype(np.float32)
+    yo = rng.uniform(-300, 300, P).astype(np.float32)
+    sgn = lambda n: np.where(rng.random(n) < 0.5, -1.0, 1.0)  # noqa: E731
+    if every_src:
+        j = np.arange(0, S, every_src)
+        src[j, j % 2] = (sgn(j.size) * big).astype(np.float32)
+    if every_pt:
+        i = np.arange(0, P, every_pt)
+        (xo if every_pt % 2 else yo)[i] = (sgn(i.size) * big).astype(np.float32)
+    return xo, yo, src
+
+
+@pytest.mark.parametrize("big,every_src,every_pt", [
+    (2.0 ** 61, 7, 0),           # some groups take the IEEE reciprocal
+    (2.0 ** 61, 0, 97),          # some waves take it for every group
+    (2.0 ** 61, 5, 131),         # both
+    (float(np.nextafter(np.float32(2.0 ** 60), np.float32(0))), 3, 89),  # just inside: rcp_rn
+    (2.0 ** 60, 3, 89)])         # exactly 2^60: the IEEE reciprocal
+def test_bit_exact_with_huge_coordinates(torch_dev, big, every_src, every_pt):
+    """Coordinates at or above 2^60 in magnitude route a group (sources) or a
+    whole wave (screen points) to the IEEE reciprocal; the results are the
+    oracle's bits either way, next to the groups that take rcp_rn."""
+    rng = np.random.default_rng(every_src * 1000 + every_pt)
+    P, S = 1000, 203
+    xo, yo, src = _mixed(rng, P, S, big, every_src, every_pt)
+    re, im = run(torch_dev, xo, yo, src, 2 * math.pi, 4000.0)
+    ro, io = oracle.huygens(xo, yo, src, 2 * math.pi, 4000.0, threads=oracle.default_threads())
+    assert_bit_exact(re, ro, "re big=%g" % big)
+    assert_bit_exact(im, io, "im big=%g" % big)
+
+
+@pytest.mark.parametrize("L", [9.9e17, 2.0 ** -50, 1.0e-20])
+def test_bit_exact_at_extreme_screen_distances(torch_dev, L):
+    """L near the largest the call takes (1e18): rcp_rn with r (r + L) near
+    2e36; L^2 < 2^-96: the general IEEE square root and the IEEE reciprocal
+    (or the two divisions where r (r + L) is subnormal).  Coordinates scaled
+    to L."""
+    rng = np.random.default_rng(int(abs(math.log2(L))))
+    P, S = 777, 131
+    scale = np.float32(min(L, 1.0) * 0.01) if L < 1 else np.float32(1.0)
+    src = np.stack([rng.uniform(-100, 100, S) * scale, rng.uniform(-100, 100, S) * scale,
+                    rng.uniform(0, 1, S) / S, rng.uniform(-math.pi, math.pi, S)], 1).astype(np.float32)
+    xo = (rng.uniform(-300, 300, P) * scale).astype(np.float32)
+    yo = (rng.uniform(-300, 300, P) * scale).astype(np.float32)
+    k = 2 * math.pi if L >= 1 else 2 * math.pi / float(scale)
+    re, im = run(torch_dev, xo, yo, src, k, L)
+    ro, io = oracle.huygens(xo, yo, src, k, L, threads=oracle.default_threads())
+    assert_bit_exact(re, ro, "re L=%g" % L)
+    assert_bit_exact(im, io, "im L=%g" % L)
