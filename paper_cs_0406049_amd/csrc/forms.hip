@@ -590,40 +590,46 @@ __device__ __forceinline__ bool huy_coord_ok(float v)
 // The terms of G sources for one screen point, added to (re, im) in source
 // order.  SQRT_RN: L^2 >= 2^-96, so rho^2 + L^2 is in the range where
 // sqrt_rn is the IEEE square root (7 fewer instructions than the general
-// sequence).  fast (wave-uniform): every r (r + L) is in rcp_rn's range (see
-// kHuyCoordMaxBits), so rcp_rn is the IEEE reciprocal and the one-reciprocal
-// form applies; otherwise, lane by lane, the IEEE reciprocal while r (r + L)
-// is a normal binary32 and two IEEE divisions where it is not.  One branch
-// per group around the quotients only: the rest of the arithmetic is shared.
+// sequence).  fast (wave-uniform): every coordinate is in range (see
+// kHuyCoordMaxBits), so rho^2 + L^2 is finite and sqrt_rn_finite is the IEEE
+// square root, and r (r + L) is in rcp_rn's range, so rcp_rn is the IEEE
+// reciprocal and the one-reciprocal form applies; otherwise, lane by lane,
+// sqrt_rn, then the IEEE reciprocal while r (r + L) is a normal binary32 and
+// two IEEE divisions where it is not.  One branch per group around the root
+// and the quotients: the rest of the arithmetic is shared.
 template <int G, bool SQRT_RN>
 __device__ __forceinline__ void huygens_terms(float px, float py, const f4 *sq, bool fast,
                                               float k, float L, float L2, float &re, float &im)
 {
-    float rho2[G], rr[G], e[G], x[G], d[G], w[G];
+    float rho2[G], r2[G], d[G], w[G];
 #pragma unroll
     for (int u = 0; u < G; ++u) {
         const float dx = px - sq[u].x;
         const float dy = py - sq[u].y;
         const float dy2 = dy * dy;
         rho2[u] = __builtin_fmaf(dx, dx, dy2);
-        rr[u] = SQRT_RN ? sqrt_rn(rho2[u] + L2) : __builtin_sqrtf(rho2[u] + L2);
-        e[u] = rr[u] + L;
-        x[u] = rr[u] * e[u];
+        r2[u] = rho2[u] + L2;
     }
     if (fast) {
+        // 2^-96 <= r2 < 2^124: sqrt_rn_finite is the IEEE square root there
 #pragma unroll
         for (int u = 0; u < G; ++u) {
-            const float g = rcp_rn(x[u]);
-            d[u] = rho2[u] * (rr[u] * g);
-            w[u] = sq[u].z * (e[u] * g);
+            const float rr = sqrt_rn_finite(r2[u]);
+            const float e = rr + L;
+            const float g = rcp_rn(rr * e);
+            d[u] = rho2[u] * (rr * g);
+            w[u] = sq[u].z * (e * g);
         }
     } else {
 #pragma unroll
         for (int u = 0; u < G; ++u) {
-            const bool normal = x[u] >= FLT_MIN && x[u] <= FLT_MAX;
-            const float g = 1.0f / x[u];
-            d[u] = normal ? rho2[u] * (rr[u] * g) : rho2[u] / e[u];
-            w[u] = normal ? sq[u].z * (e[u] * g) : sq[u].z / rr[u];
+            const float rr = SQRT_RN ? sqrt_rn(r2[u]) : __builtin_sqrtf(r2[u]);
+            const float e = rr + L;
+            const float x = rr * e;
+            const bool normal = x >= FLT_MIN && x <= FLT_MAX;
+            const float g = 1.0f / x;
+            d[u] = normal ? rho2[u] * (rr * g) : rho2[u] / e;
+            w[u] = normal ? sq[u].z * (e * g) : sq[u].z / rr;
         }
     }
 #pragma unroll

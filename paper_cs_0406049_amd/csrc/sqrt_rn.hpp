@@ -36,4 +36,19 @@ __device__ __forceinline__ float sqrt_rn(float x)
     return r_above > 0.0f ? above : t;
 }
 
+// Five instructions for finite arguments: the hardware reciprocal square
+// root estimate y, the root estimate s = x y, and one Newton correction
+// with a fused multiply-add, s + (x - s^2) (y / 2).  On the GPU this equals
+// IEEE sqrt(x) for every binary32 2^-96 <= x <= FLT_MAX (an exhaustive GPU
+// test checks it); at +inf it gives NaN, so callers use it only where the
+// argument is known to be finite.
+__device__ __forceinline__ float sqrt_rn_finite(float x)
+{
+    const float y = __builtin_amdgcn_rsqf(x);
+    const float s = x * y;
+    const float h = 0.5f * y;
+    const float r = __builtin_fmaf(-s, s, x);
+    return __builtin_fmaf(r, h, s);
+}
+
 }  // namespace mi355

@@ -1,6 +1,6 @@
-// sqrt_rn_check.hip -- test helper: compares the library's sqrt_rn with the
-// compiler's IEEE (correctly rounded) binary32 square root on every bit
-// pattern in [lo, hi], on the GPU.  With `planted` set it compares against
+// sqrt_rn_check.hip -- test helper: compares the library's sqrt_rn (and
+// sqrt_rn_finite) with the compiler's IEEE (correctly rounded) binary32
+// square root on every bit pattern in [lo, hi], on the GPU.  With `planted` set it compares against
 // the IEEE root of the next binary32 instead, a difference the check must
 // report (so that a check that sees nothing cannot pass).  Built by __graft_entry__.build() into
 // tests/native/libsqrt_rn_check.so; used by tests/test_gpu_sqrt_rn.py.
@@ -10,6 +10,7 @@
 
 #include "../../paper_cs_0406049_amd/csrc/sqrt_rn.hpp"
 
+template <int FINITE>
 __global__ void k_sqrt_rn_check(uint32_t lo, uint32_t hi, int planted,
                                 unsigned long long *mismatches, uint32_t *first_bad)
 {
@@ -17,7 +18,7 @@ __global__ void k_sqrt_rn_check(uint32_t lo, uint32_t hi, int planted,
     for (uint64_t b = (uint64_t)lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b <= hi;
          b += stride) {
         const float x = __builtin_bit_cast(float, (uint32_t)b);
-        const float got = mi355::sqrt_rn(x);
+        const float got = FINITE ? mi355::sqrt_rn_finite(x) : mi355::sqrt_rn(x);
         const float want = __builtin_sqrtf(
             planted ? __builtin_bit_cast(float, (uint32_t)b + 1u) : x);
         const bool same = __builtin_bit_cast(uint32_t, got) == __builtin_bit_cast(uint32_t, want) ||
@@ -31,8 +32,9 @@ __global__ void k_sqrt_rn_check(uint32_t lo, uint32_t hi, int planted,
 
 // Returns 0 on success (counts in *mismatches and the smallest mismatching
 // bit pattern in *first_bad, 0xffffffff if none), else a hipError_t.
-extern "C" __attribute__((visibility("default"))) int sqrt_rn_check(
-    uint32_t lo, uint32_t hi, int planted, unsigned long long *mismatches, uint32_t *first_bad)
+template <int FINITE>
+static int run_check(uint32_t lo, uint32_t hi, int planted, unsigned long long *mismatches,
+                     uint32_t *first_bad)
 {
     if (lo > hi || !mismatches || !first_bad)
         return (int)hipErrorInvalidValue;
@@ -48,8 +50,8 @@ extern "C" __attribute__((visibility("default"))) int sqrt_rn_check(
     if (e == hipSuccess)
         e = hipMemcpy(d_first, &none, sizeof none, hipMemcpyHostToDevice);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_sqrt_rn_check, dim3(4096), dim3(256), 0, 0, lo, hi, planted, d_count,
-                           d_first);
+        hipLaunchKernelGGL(k_sqrt_rn_check<FINITE>, dim3(4096), dim3(256), 0, 0, lo, hi, planted,
+                           d_count, d_first);
         e = hipGetLastError();
     }
     if (e == hipSuccess)
@@ -61,4 +63,18 @@ extern "C" __attribute__((visibility("default"))) int sqrt_rn_check(
     if (d_first)
         (void)hipFree(d_first);
     return (int)e;
+}
+
+// sqrt_rn, and sqrt_rn_finite (the five-instruction root for finite
+// arguments), against the IEEE square root.
+extern "C" __attribute__((visibility("default"))) int sqrt_rn_check(
+    uint32_t lo, uint32_t hi, int planted, unsigned long long *mismatches, uint32_t *first_bad)
+{
+    return run_check<0>(lo, hi, planted, mismatches, first_bad);
+}
+
+extern "C" __attribute__((visibility("default"))) int sqrt_rn_finite_check(
+    uint32_t lo, uint32_t hi, int planted, unsigned long long *mismatches, uint32_t *first_bad)
+{
+    return run_check<1>(lo, hi, planted, mismatches, first_bad);
 }

@@ -34,12 +34,14 @@ def test_every_declared_symbol_is_exported(L):
     assert set(names) == set(_capi._SIGNATURES), "binding and header disagree"
 
 
-@pytest.mark.parametrize("name", ["sqrt_rn_check", "rcp_rn_check"])
-def test_check_helpers_are_built_and_export_their_entry(L, name):
+@pytest.mark.parametrize("lib_name,name", [("sqrt_rn_check", "sqrt_rn_check"),
+                                           ("sqrt_rn_check", "sqrt_rn_finite_check"),
+                                           ("rcp_rn_check", "rcp_rn_check")])
+def test_check_helpers_are_built_and_export_their_entries(L, lib_name, name):
     """The GPU tests' square-root and reciprocal check libraries (built beside
-    the tests by __graft_entry__.build()) export their one entry point."""
+    the tests by __graft_entry__.build()) export their entry points."""
     import subprocess
-    lib = os.path.join(ROOT, "tests", "native", "lib%s.so" % name)
+    lib = os.path.join(ROOT, "tests", "native", "lib%s.so" % lib_name)
     if not os.path.exists(lib):
         hipbuild.build_test_helpers()
     out = subprocess.run(["nm", "-D", "--defined-only", lib], capture_output=True,

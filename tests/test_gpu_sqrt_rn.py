@@ -1,7 +1,9 @@
-"""The Huygens kernel's square root (sqrt_rn in csrc/sqrt_rn.hpp) is the IEEE
-correctly rounded binary32 square root on every argument it can see:
-every bit pattern from 2^-96 up to +inf, and NaN, checked exhaustively on
-the GPU against the compiler's IEEE sqrt."""
+"""The Huygens kernel's square roots (csrc/sqrt_rn.hpp) are the IEEE
+correctly rounded binary32 square root on every argument they can see,
+checked exhaustively on the GPU against the compiler's IEEE sqrt: sqrt_rn on
+every bit pattern from 2^-96 up to +inf and on NaN, sqrt_rn_finite (the
+five-instruction root of the kernel's guarded path) on every bit pattern
+from 2^-96 to the largest finite binary32."""
 import ctypes
 import os
 
@@ -19,13 +21,15 @@ def check():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     assert os.path.exists(LIB), "tests/native/libsqrt_rn_check.so is not built (__graft_entry__.build())"
     L = ctypes.CDLL(LIB)
-    L.sqrt_rn_check.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
-                                ctypes.POINTER(ctypes.c_ulonglong), ctypes.POINTER(ctypes.c_uint32)]
-    L.sqrt_rn_check.restype = ctypes.c_int
+    for fn in (L.sqrt_rn_check, L.sqrt_rn_finite_check):
+        fn.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                       ctypes.POINTER(ctypes.c_ulonglong), ctypes.POINTER(ctypes.c_uint32)]
+        fn.restype = ctypes.c_int
 
-    def run(lo, hi, planted=0):
+    def run(lo, hi, planted=0, finite=False):
         n, first = ctypes.c_ulonglong(0), ctypes.c_uint32(0)
-        rc = L.sqrt_rn_check(lo, hi, planted, ctypes.byref(n), ctypes.byref(first))
+        fn = L.sqrt_rn_finite_check if finite else L.sqrt_rn_check
+        rc = fn(lo, hi, planted, ctypes.byref(n), ctypes.byref(first))
         assert rc == 0, "HIP error %d" % rc
         return n.value, first.value
     return run
@@ -52,3 +56,21 @@ def test_the_check_sees_a_planted_difference(check):
     lo, hi = 0x3F800000, 0x3F800000 + (1 << 20)      # [1, 1.125)
     n, first = check(lo, hi, planted=1)
     assert (hi - lo) // 4 < n < hi - lo + 1, n
+
+
+def test_finite_root_on_every_argument_from_2_to_minus_96_to_the_largest_finite(check):
+    n, first = check(0x0F800000, 0x7F7FFFFF, finite=True)
+    assert n == 0, "%d mismatches, first at bits %08x" % (n, first)
+
+
+def test_finite_root_is_not_the_ieee_root_at_infinity(check):
+    """+inf gives NaN: the kernel takes sqrt_rn_finite only for arguments
+    its coordinate guard keeps below 2^124."""
+    n, first = check(0x7F800000, 0x7F800000, finite=True)
+    assert n == 1 and first == 0x7F800000
+
+
+def test_finite_root_check_sees_a_planted_difference(check):
+    lo, hi = 0x3F800000, 0x3F800000 + (1 << 20)      # [1, 1.125]
+    n, first = check(lo, hi, planted=1, finite=True)
+    assert (hi - lo) // 4 < n <= hi - lo + 1, n
