@@ -518,7 +518,7 @@ def bench_interleaved(torch, reps, plain_gbs, x_host):
     return res
 
 
-HUYGENS_OPS = 96 / 2    # VALU instructions per (point, source) pair in the loop's ISA
+HUYGENS_OPS = 90 / 2    # VALU instructions per (point, source) pair in the loop's ISA
 
 
 def bench_huygens(torch, reps):

@@ -642,21 +642,23 @@ __device__ __forceinline__ void huygens_terms(float px, float py, const f4 *sq, 
 }
 
 // Whether every source coordinate of a group is below 2^60 in magnitude:
-// one comparison of the largest magnitude bit pattern, no branches (the
-// values are wave-uniform, so this stays on the scalar unit).  The elements
+// per source one comparison of the larger magnitude bit pattern, no
+// branches (the values are wave-uniform, so this stays on the scalar unit).  The elements
 // are copied to scalars first: __builtin_bit_cast applied to a vector
 // element reads the vector's first element with this compiler.
 template <int G>
 __device__ __forceinline__ bool huy_sources_ok(const f4 *sq)
 {
-    uint32_t m = 0;
+    bool ok = true;
 #pragma unroll
     for (int u = 0; u < G; ++u) {
         const float x = sq[u].x, y = sq[u].y;
-        m = max(m, __builtin_bit_cast(uint32_t, x) & 0x7FFFFFFFu);
-        m = max(m, __builtin_bit_cast(uint32_t, y) & 0x7FFFFFFFu);
+        const uint32_t m = __builtin_amdgcn_readfirstlane(
+            max(__builtin_bit_cast(uint32_t, x) & 0x7FFFFFFFu,
+                __builtin_bit_cast(uint32_t, y) & 0x7FFFFFFFu));
+        ok = ok & (m < kHuyCoordMaxBits);
     }
-    return m < kHuyCoordMaxBits;
+    return ok;
 }
 
 // WRAP = 0: source j is src[j] (the sum).  WRAP = 8: source j is src[j % 8],
@@ -681,6 +683,10 @@ __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *y
     const int32_t lo = (int32_t)min<int64_t>(S, (int64_t)blk * per);
     const int32_t cnt = (int32_t)min<int64_t>(S - lo, per);
     const int32_t full = cnt / kHuyGroup * kHuyGroup;  // sources in whole groups
+    // k in a vector register: theta = fma(k, d, phi) then reads one scalar
+    // operand (phi), which a vector instruction can take without a copy
+    float kv;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(kv) : "s"(k));
     for (int64_t base = (int64_t)blockIdx.x * kHuyPoints; base < P;
          base += (int64_t)gridDim.x * kHuyPoints) {  // workgroup-uniform loop
         const int64_t i = base + lane;
@@ -706,7 +712,7 @@ __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *y
 #pragma unroll
             for (int u = 0; u < kHuyGroup; ++u)
                 nxt[u] = src[at(lo + nq + u)];
-            huygens_terms<kHuyGroup, SQRT_RN>(px, py, cur, fast, k, L, L2, ar, ai);
+            huygens_terms<kHuyGroup, SQRT_RN>(px, py, cur, fast, kv, L, L2, ar, ai);
             // the next group's path, decided once its sources have arrived
             fast = pts_ok & huy_sources_ok<kHuyGroup>(nxt);
 #pragma unroll
@@ -715,7 +721,7 @@ __global__ void __launch_bounds__(256) k_huygens(const float *xo, const float *y
         }
         for (int32_t q = full; q < cnt; ++q) {
             const f4 sq = src[at(lo + q)];
-            huygens_terms<1, SQRT_RN>(px, py, &sq, pts_ok & huy_sources_ok<1>(&sq), k, L, L2,
+            huygens_terms<1, SQRT_RN>(px, py, &sq, pts_ok & huy_sources_ok<1>(&sq), kv, L, L2,
                                       ar, ai);
         }
         part_re[blk][lane] = ar;
