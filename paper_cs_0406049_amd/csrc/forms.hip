@@ -559,9 +559,9 @@ __global__ void __launch_bounds__(256) k_fit_reduce(const float *partial, const 
 // phi_j)), the path difference as rho^2 / (r + L), both quotients from one
 // reciprocal: e = r + L, g = 1 / (r e), d = rho^2 (r g), w = a (e g), each
 // operation rounded (two divisions, d = rho^2 / e and w = a / r, where r e
-// is not a normal binary32).  The sources are summed in kHuyBlocks contiguous blocks
-// of ceil(S / kHuyBlocks), each in source order with fma from +0, and the
-// block sums are added in block order.  One wave per block: a 256-thread
+// is not a normal binary32).  The sources are summed in kHuyBlocks
+// contiguous blocks of ceil(S / kHuyBlocks), each in source order with fma
+// from +0, and the block sums are added in block order.  One wave per block: a 256-thread
 // workgroup takes 64 screen points, wave b sums block b for all 64 and the
 // four partial fields meet in LDS.  Four waves per point give the
 // diffraction workload (262,144 points) 16,384 waves instead of 4096, enough
@@ -575,11 +575,12 @@ __global__ void __launch_bounds__(256) k_fit_reduce(const float *partial, const 
 constexpr int kHuyGroup = 2;
 constexpr int kHuyBlocks = 4;
 constexpr int kHuyPoints = 256 / kHuyBlocks;  // screen points per workgroup (one wave)
-// rcp_rn serves the reciprocal when every coordinate of the wave's points
-// and of the group's sources is below 2^60 in magnitude and 2^-48 <= L <
-// 2^60 (checked by the launcher): then rho^2 < 2^123, r < 2^62, r + L < 2^63
-// and 2^-96 <= r (r + L) < 2^125, inside rcp_rn's range.  Otherwise (huge,
-// infinite or NaN coordinates) the group takes the IEEE division.
+// The short square root and rcp_rn serve a group when every coordinate of
+// the wave's points and of the group's sources is below 2^60 in magnitude
+// and 2^-48 <= L < 2^60 (checked by the launcher): then 2^-96 <= rho^2 + L^2
+// < 2^124, r < 2^62, r + L < 2^63 and 2^-96 <= r (r + L) < 2^125, inside
+// both helpers' ranges.  Otherwise (huge, infinite or NaN coordinates) the
+// group takes sqrt_rn and the IEEE reciprocal, or the two divisions.
 constexpr uint32_t kHuyCoordMaxBits = 0x5D800000u;  // 2^60
 
 __device__ __forceinline__ bool huy_coord_ok(float v)
@@ -643,9 +644,11 @@ __device__ __forceinline__ void huygens_terms(float px, float py, const f4 *sq, 
 
 // Whether every source coordinate of a group is below 2^60 in magnitude:
 // per source one comparison of the larger magnitude bit pattern, no
-// branches (the values are wave-uniform, so this stays on the scalar unit).  The elements
-// are copied to scalars first: __builtin_bit_cast applied to a vector
-// element reads the vector's first element with this compiler.
+// branches.  The values are wave-uniform; the read-first-lane of each
+// per-source maximum keeps the compiler from merging the comparisons into a
+// vector three-input maximum, so the check stays on the scalar unit.  The
+// elements are copied to scalars first: __builtin_bit_cast applied to a
+// vector element reads the vector's first element with this compiler.
 template <int G>
 __device__ __forceinline__ bool huy_sources_ok(const f4 *sq)
 {
