@@ -452,26 +452,37 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_sinusoid_fit(
     const int64_t nparts = gridDim.x;
     const int32_t Kpad = kgroups * 64;
 
-    // phase 1: two samples per thread, the forward model in k order from +0
+    // phase 1: two samples per thread, each the forward model in k order from
+    // +0; both samples in one pass over k, so that each frequency's
+    // parameters serve two terms (and the two chains overlap)
     float sq = 0.0f;
+    float ti[2], acc[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int64_t i = base + (int)threadIdx.x + h * 64 * kAdjWaves;
+        ti[h] = i < N ? t[i] : 0.0f;
+        acc[h] = 0.0f;
+    }
+#pragma unroll 4
+    for (int32_t k = 0; k < K; ++k) {
+        const float wk = w[k], pk = phi[k], ak = A[k];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            float sv, cv;
+            sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(wk, ti[h], pk), sv, cv);
+            acc[h] = __builtin_fmaf(ak, sv, acc[h]);
+        }
+    }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int li = (int)threadIdx.x + h * 64 * kAdjWaves;
         const int64_t i = base + li;
-        float ti = 0.0f, r = 0.0f;
+        float r = 0.0f;
         if (i < N) {
-            ti = t[i];
-            float acc = 0.0f;
-#pragma unroll 4
-            for (int32_t k = 0; k < K; ++k) {
-                float sv, cv;
-                sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(w[k], ti, phi[k]), sv, cv);
-                acc = __builtin_fmaf(A[k], sv, acc);
-            }
-            r = acc - y_obs[i];
+            r = acc[h] - y_obs[i];
             sq = __builtin_fmaf(r, r, sq);
         }
-        ts[li] = ti;
+        ts[li] = ti[h];
         rs[li] = r;
     }
     red[threadIdx.x] = sq;
