@@ -519,6 +519,11 @@ def bench_interleaved(torch, reps, plain_gbs, x_host):
 
 
 HUYGENS_OPS = 90 / 2    # VALU instructions per (point, source) pair in the loop's ISA
+# of which v_rsq_f32 and v_rcp_f32 (one each per pair) are transcendental
+# instructions, issued at a quarter of the rate of the others: each takes four
+# issue slots, so the pair needs 45 + 2 * 3 = 51 slots
+HUYGENS_TRANSCENDENTALS = 4 / 2
+HUYGENS_SLOTS = HUYGENS_OPS + 3 * HUYGENS_TRANSCENDENTALS
 
 
 def bench_huygens(torch, reps):
@@ -574,7 +579,11 @@ def bench_huygens(torch, reps):
             "frac_of_term_ceiling": round(t_ms / ms, 4),
             "composed_plain_kernel_plus_torch_ms": round(c_ms, 3),
             "speedup_vs_composed": round(c_ms / ms, 2),
-            "roofline": alu_roofline(tops, HUYGENS_OPS, ceil)}
+            "roofline": dict(alu_roofline(tops, HUYGENS_OPS, ceil),
+                             transcendentals_per_pair=HUYGENS_TRANSCENDENTALS,
+                             issue_slots_per_pair=HUYGENS_SLOTS,
+                             frac_of_issue_slots=round(
+                                 tops * HUYGENS_SLOTS / HUYGENS_OPS / VALU_PEAK_TOPS, 4))}
 
 
 def bench_serve(torch, plain_gelem_s):

@@ -580,8 +580,8 @@ __global__ void __launch_bounds__(256) k_fit_reduce(const float *partial, const 
 // them.  The source table (x, y, a, phi) is read with wave-uniform float4
 // scalar loads, and the loads of the next kHuyGroup sources are issued
 // before the current group is evaluated, so their latency hides behind
-// that arithmetic.  The square root and the reciprocal are correctly
-// rounded.
+// that arithmetic; the group's sine-cosine pairs are evaluated in lockstep.
+// The square root and the reciprocal are correctly rounded.
 
 constexpr int kHuyGroup = 2;
 constexpr int kHuyBlocks = 4;
@@ -597,6 +597,34 @@ constexpr uint32_t kHuyCoordMaxBits = 0x5D800000u;  // 2^60
 __device__ __forceinline__ bool huy_coord_ok(float v)
 {
     return (__builtin_bit_cast(uint32_t, v) & 0x7FFFFFFFu) < kHuyCoordMaxBits;
+}
+
+template <int N> using huy_vec = float __attribute__((ext_vector_type(N)));
+
+// N sine-cosine pairs of the first method (fused arithmetic) in lockstep:
+// elementwise exactly the operations of pair_exact<Fused, Normalized>, in the
+// same order, written on N-element vectors so that the N chains interleave
+// instruction by instruction (without packed arithmetic each vector operation
+// becomes N scalar ones).
+template <int N>
+__device__ __forceinline__ void pair_exact_xn(huy_vec<N> th, huy_vec<N> &s, huy_vec<N> &c)
+{
+    using V = huy_vec<N>;
+    using S = Series<Method::Normalized>;
+    auto fma_v = [](V a, V b, V d) { return __builtin_elementwise_fma(a, b, d); };
+    const V t = th * kInvTwoPi;
+    const V x = t - __builtin_elementwise_roundeven(t);  // ties to even, as rint
+    const V x2 = x * x;
+    const V ps = fma_v(x2, fma_v(x2, fma_v(x2, (V)S::ss4, (V)S::ss3), (V)S::ss2), (V)S::ss1);
+    const V c1 = fma_v(x2, fma_v(x2, fma_v(x2, (V)S::cc3, (V)S::cc2), (V)S::cc1), (V)1.0f);
+    const V s1 = x * ps;
+    const V s2 = 2.0f * (s1 * c1);                          // eq. (1)
+    const V c2 = fma_v(-s1, s1, c1 * c1);
+    const V m = fma_v(-s2, s2, fma_v(-c2, c2, (V)2.0f));  // 2 - c2^2 - s2^2
+    const V s3 = 2.0f * (s2 * c2);
+    const V c3 = fma_v(-s2, s2, c2 * c2);
+    s = s3 * m;
+    c = c3 * m;
 }
 
 // The terms of G sources for one screen point, added to (re, im) in source
@@ -644,35 +672,47 @@ __device__ __forceinline__ void huygens_terms(float px, float py, const f4 *sq, 
             w[u] = normal ? sq[u].z * (e * g) : sq[u].z / rr;
         }
     }
+    if constexpr (G > 1) {
+        huy_vec<G> th, sv, cv;
 #pragma unroll
-    for (int u = 0; u < G; ++u) {
+        for (int u = 0; u < G; ++u)
+            th[u] = __builtin_fmaf(k, d[u], sq[u].w);
+        pair_exact_xn<G>(th, sv, cv);
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            re = __builtin_fmaf(w[u], cv[u], re);
+            im = __builtin_fmaf(w[u], sv[u], im);
+        }
+    } else {
         float sv, cv;
-        sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(k, d[u], sq[u].w), sv, cv);
-        re = __builtin_fmaf(w[u], cv, re);
-        im = __builtin_fmaf(w[u], sv, im);
+        sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(k, d[0], sq[0].w), sv, cv);
+        re = __builtin_fmaf(w[0], cv, re);
+        im = __builtin_fmaf(w[0], sv, im);
     }
 }
 
-// Whether every source coordinate of a group is below 2^60 in magnitude:
-// per source one comparison of the larger magnitude bit pattern, no
-// branches.  The values are wave-uniform; the read-first-lane of each
-// per-source maximum keeps the compiler from merging the comparisons into a
-// vector three-input maximum, so the check stays on the scalar unit.  The
-// elements are copied to scalars first: __builtin_bit_cast applied to a
-// vector element reads the vector's first element with this compiler.
+// Whether every source coordinate of a group is below 2^60 in magnitude: the
+// running maximum of the magnitude bit patterns against 2^60, no branches.
+// The values are wave-uniform; the empty asm statements pin each maximum to a
+// scalar register, which keeps the compiler from merging them into a vector
+// three-input maximum (a vector result the branch would then wait for), so
+// the check stays on the scalar unit.  The elements are copied to scalars
+// first: __builtin_bit_cast applied to a vector element reads the vector's
+// first element with this compiler.
 template <int G>
 __device__ __forceinline__ bool huy_sources_ok(const f4 *sq)
 {
-    bool ok = true;
+    uint32_t acc = 0;
 #pragma unroll
     for (int u = 0; u < G; ++u) {
         const float x = sq[u].x, y = sq[u].y;
-        const uint32_t m = __builtin_amdgcn_readfirstlane(
-            max(__builtin_bit_cast(uint32_t, x) & 0x7FFFFFFFu,
-                __builtin_bit_cast(uint32_t, y) & 0x7FFFFFFFu));
-        ok = ok & (m < kHuyCoordMaxBits);
+        uint32_t m = max(__builtin_bit_cast(uint32_t, x) & 0x7FFFFFFFu,
+                         __builtin_bit_cast(uint32_t, y) & 0x7FFFFFFFu);
+        asm("" : "+s"(m));
+        acc = max(acc, m);
+        asm("" : "+s"(acc));
     }
-    return ok;
+    return acc < kHuyCoordMaxBits;
 }
 
 // WRAP = 0: source j is src[j] (the sum).  WRAP = 8: source j is src[j % 8],
