@@ -53,7 +53,8 @@ def build(verbose: bool = False) -> str:
 
 # GPU test helpers built beside the tests (not part of the library).
 TEST_HELPERS = [("tests/native/sqrt_rn_check.hip", "tests/native/libsqrt_rn_check.so"),
-                ("tests/native/rcp_rn_check.hip", "tests/native/librcp_rn_check.so")]
+                ("tests/native/rcp_rn_check.hip", "tests/native/librcp_rn_check.so"),
+                ("tests/native/lockstep_check.hip", "tests/native/liblockstep_check.so")]
 
 
 def build_test_helpers(verbose: bool = False) -> None:

@@ -599,34 +599,6 @@ __device__ __forceinline__ bool huy_coord_ok(float v)
     return (__builtin_bit_cast(uint32_t, v) & 0x7FFFFFFFu) < kHuyCoordMaxBits;
 }
 
-template <int N> using huy_vec = float __attribute__((ext_vector_type(N)));
-
-// N sine-cosine pairs of the first method (fused arithmetic) in lockstep:
-// elementwise exactly the operations of pair_exact<Fused, Normalized>, in the
-// same order, written on N-element vectors so that the N chains interleave
-// instruction by instruction (without packed arithmetic each vector operation
-// becomes N scalar ones).
-template <int N>
-__device__ __forceinline__ void pair_exact_xn(huy_vec<N> th, huy_vec<N> &s, huy_vec<N> &c)
-{
-    using V = huy_vec<N>;
-    using S = Series<Method::Normalized>;
-    auto fma_v = [](V a, V b, V d) { return __builtin_elementwise_fma(a, b, d); };
-    const V t = th * kInvTwoPi;
-    const V x = t - __builtin_elementwise_roundeven(t);  // ties to even, as rint
-    const V x2 = x * x;
-    const V ps = fma_v(x2, fma_v(x2, fma_v(x2, (V)S::ss4, (V)S::ss3), (V)S::ss2), (V)S::ss1);
-    const V c1 = fma_v(x2, fma_v(x2, fma_v(x2, (V)S::cc3, (V)S::cc2), (V)S::cc1), (V)1.0f);
-    const V s1 = x * ps;
-    const V s2 = 2.0f * (s1 * c1);                          // eq. (1)
-    const V c2 = fma_v(-s1, s1, c1 * c1);
-    const V m = fma_v(-s2, s2, fma_v(-c2, c2, (V)2.0f));  // 2 - c2^2 - s2^2
-    const V s3 = 2.0f * (s2 * c2);
-    const V c3 = fma_v(-s2, s2, c2 * c2);
-    s = s3 * m;
-    c = c3 * m;
-}
-
 // The terms of G sources for one screen point, added to (re, im) in source
 // order.  SQRT_RN: L^2 >= 2^-96, so rho^2 + L^2 is in the range where
 // sqrt_rn is the IEEE square root (7 fewer instructions than the general
@@ -673,11 +645,11 @@ __device__ __forceinline__ void huygens_terms(float px, float py, const f4 *sq, 
         }
     }
     if constexpr (G > 1) {
-        huy_vec<G> th, sv, cv;
+        fvec<G> th, sv, cv;  // the group's pairs in lockstep
 #pragma unroll
         for (int u = 0; u < G; ++u)
             th[u] = __builtin_fmaf(k, d[u], sq[u].w);
-        pair_exact_xn<G>(th, sv, cv);
+        pair_exact<Arith::Fused, Method::Normalized>(th, sv, cv);
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             re = __builtin_fmaf(w[u], cv[u], re);

@@ -1,7 +1,8 @@
 // sincos_core.hpp -- device arithmetic of the branch-free single-precision
 // sine-cosine pair (Mendenhall 2004), for gfx950.
 //
-// One lane computes one pair with binary32 VALU operations only: no branch,
+// One lane computes one pair (or N pairs in lockstep, on fvec<N> values)
+// with binary32 VALU operations only: no branch,
 // no table, no FP64, no packed FP32 (the library is built with packed FP32
 // disabled), IEEE subnormals kept (no flush).  The method of Sec. II:
 //   reduce   the angle times 1/(2 pi), less its nearest integer: the fraction
@@ -28,6 +29,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 namespace mi355 {
 
@@ -77,80 +80,112 @@ static_assert(Series<Method::Arctan>::cc1 == -1.2341299769f, "cc1");
 static_assert(Series<Method::Arctan>::cc2 == 0.2465220241f, "cc2");
 static_assert(Series<Method::Arctan>::cc3 == -0.0123926179f, "cc3");
 
+// The arithmetic below is written for a value type V: float (one pair per
+// lane), or fvec<N>, N pairs per lane in lockstep.  On a vector every
+// operation is the scalar one applied to each element (the library is built
+// without packed FP32, so each becomes N scalar instructions, the N chains
+// interleaved), hence each element's bits are the scalar path's.
+template <int N> using fvec = float __attribute__((ext_vector_type(N)));
+
 // a*b + c and c - a*b.  Fused: one rounding (v_fma_f32).  Split: product and
 // sum rounded separately; the translation unit is compiled with
 // -ffp-contract=off, so the compiler cannot fuse them.
-template <Arith A> __device__ __forceinline__ float mul_add(float a, float b, float c)
+template <typename V> __device__ __forceinline__ V fma_v(V a, V b, V c)
+{
+    if constexpr (std::is_same_v<V, float>)
+        return __builtin_fmaf(a, b, c);
+    else
+        return __builtin_elementwise_fma(a, b, c);
+}
+
+template <Arith A, typename V> __device__ __forceinline__ V mul_add(V a, V b, V c)
 {
     if constexpr (A == Arith::Fused) {
-        return __builtin_fmaf(a, b, c);
+        return fma_v(a, b, c);
     } else {
-        const float p = a * b;
+        const V p = a * b;
         return p + c;
     }
 }
 
-template <Arith A> __device__ __forceinline__ float mul_sub_from(float a, float b, float c)
+template <Arith A, typename V> __device__ __forceinline__ V mul_sub_from(V a, V b, V c)
 {
     if constexpr (A == Arith::Fused) {
-        return __builtin_fmaf(-a, b, c);
+        return fma_v(-a, b, c);
     } else {
-        const float p = a * b;
+        const V p = a * b;
         return c - p;
     }
 }
 
-// A sine-cosine pair.
-struct Pair {
-    float s, c;
+// A sine-cosine pair (or N of them).
+template <typename V> struct PairT {
+    V s, c;
 };
+using Pair = PairT<float>;
 
-// Reduction: theta / (2 pi) less its nearest integer.
-__device__ __forceinline__ float reduce_turns(float theta)
+// Reduction: theta / (2 pi) less its nearest integer (round to nearest even).
+template <typename V> __device__ __forceinline__ V reduce_turns(V theta)
 {
-    const float turns = theta * kInvTwoPi;
-    return turns - __builtin_rintf(turns);
+    const V turns = theta * kInvTwoPi;
+    if constexpr (std::is_same_v<V, float>)
+        return turns - __builtin_rintf(turns);
+    else
+        return turns - __builtin_elementwise_rint(turns);
 }
 
 // Horner's rule in x2: k0 + x2 (k1 + x2 (k2 + ...)).
-template <Arith A> __device__ __forceinline__ float horner(float, float top) { return top; }
-template <Arith A, typename... R>
-__device__ __forceinline__ float horner(float x2, float k0, R... rest)
+template <Arith A, typename V> __device__ __forceinline__ V horner(V, float top)
 {
-    return mul_add<A>(x2, horner<A>(x2, rest...), k0);
+    return (V)top;
+}
+template <Arith A, typename V, typename... R>
+__device__ __forceinline__ V horner(V x2, float k0, R... rest)
+{
+    return mul_add<A>(x2, horner<A>(x2, rest...), (V)k0);
 }
 
-// Series: (sin, cos) of the quarter angle pi x / 2.
-template <Arith A, Method M> __device__ __forceinline__ Pair quarter_pair(float x)
+// Series: (sin, cos) of the quarter angle pi x / 2.  On vectors both
+// polynomials are written before the product x * (sine polynomial): the same
+// operations, in an order from which the compiler schedules N interleaved
+// chains better (measured on the Huygens kernel).
+template <Arith A, Method M, typename V> __device__ __forceinline__ PairT<V> quarter_pair(V x)
 {
     using S = Series<M>;
-    const float x2 = x * x;
-    return {x * horner<A>(x2, S::ss1, S::ss2, S::ss3, S::ss4),
-            horner<A>(x2, 1.0f, S::cc1, S::cc2, S::cc3)};
+    const V x2 = x * x;
+    if constexpr (std::is_same_v<V, float>) {
+        return {x * horner<A>(x2, S::ss1, S::ss2, S::ss3, S::ss4),
+                horner<A>(x2, 1.0f, S::cc1, S::cc2, S::cc3)};
+    } else {
+        const V ps = horner<A>(x2, S::ss1, S::ss2, S::ss3, S::ss4);
+        const V pc = horner<A>(x2, 1.0f, S::cc1, S::cc2, S::cc3);
+        return {x * ps, pc};
+    }
 }
 
 // eq. (1): (sin 2u, cos 2u) = (2 s c, c^2 - s^2).
-template <Arith A> __device__ __forceinline__ Pair double_angle(Pair p)
+template <Arith A, typename V = float> __device__ __forceinline__ PairT<V> double_angle(PairT<V> p)
 {
     return {2.0f * (p.s * p.c), mul_sub_from<A>(p.s, p.s, p.c * p.c)};
 }
 
 // Magnitude factor 1/(1 + e) from a pair with |p|^2 = 1 + e.
-template <Arith A, Method M> __device__ __forceinline__ float norm_factor(Pair p)
+template <Arith A, Method M, typename V = float>
+__device__ __forceinline__ V norm_factor(PairT<V> p)
 {
     if constexpr (M == Method::Normalized)
-        return mul_sub_from<A>(p.s, p.s, mul_sub_from<A>(p.c, p.c, 2.0f));  // 1 - e
+        return mul_sub_from<A>(p.s, p.s, mul_sub_from<A>(p.c, p.c, (V)2.0f));  // 1 - e
     else
-        return 1.0f / mul_add<A>(p.s, p.s, p.c * p.c);  // IEEE division, correctly rounded
+        return (V)1.0f / mul_add<A>(p.s, p.s, p.c * p.c);  // IEEE division, correctly rounded
 }
 
 // The method with FUSED or SPLIT arithmetic.
-template <Arith A, Method M>
-__device__ __forceinline__ void pair_exact(float theta, float &s, float &c)
+template <Arith A, Method M, typename V>
+__device__ __forceinline__ void pair_exact(V theta, V &s, V &c)
 {
-    const Pair half = double_angle<A>(quarter_pair<A, M>(reduce_turns(theta)));
-    const float m = norm_factor<A, M>(half);  // |half|^2 is the final magnitude
-    const Pair whole = double_angle<A>(half);
+    const PairT<V> half = double_angle<A, V>(quarter_pair<A, M>(reduce_turns(theta)));
+    const V m = norm_factor<A, M, V>(half);  // |half|^2 is the final magnitude
+    const PairT<V> whole = double_angle<A, V>(half);
     s = whole.s * m;
     c = whole.c * m;
 }

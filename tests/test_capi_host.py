@@ -36,9 +36,10 @@ def test_every_declared_symbol_is_exported(L):
 
 @pytest.mark.parametrize("lib_name,name", [("sqrt_rn_check", "sqrt_rn_check"),
                                            ("sqrt_rn_check", "sqrt_rn_finite_check"),
-                                           ("rcp_rn_check", "rcp_rn_check")])
+                                           ("rcp_rn_check", "rcp_rn_check"),
+                                           ("lockstep_check", "lockstep_check")])
 def test_check_helpers_are_built_and_export_their_entries(L, lib_name, name):
-    """The GPU tests' square-root and reciprocal check libraries (built beside
+    """The GPU tests' square-root, reciprocal and lockstep check libraries (built beside
     the tests by __graft_entry__.build()) export their entry points."""
     import subprocess
     lib = os.path.join(ROOT, "tests", "native", "lib%s.so" % lib_name)
