@@ -156,10 +156,12 @@ def cpu_baseline(x_host, arith: int):
 VALU_PEAK_TOPS = 157.3 / 2
 ALU_WARM_MS = 30.0      # compute before timing an ALU-bound kernel (clock ramp)
 SERVE_REPLAYS = 5       # open-loop replays of the served workload per configuration
-# VALU instructions per (sample, frequency) pair in the kernels' inner loops,
-# counted in the gfx950 assembly: 89 per 4 pairs (forward), 233 per 8 (adjoint).
-SINUSOID_FWD_OPS = 89 / 4
-SINUSOID_ADJ_OPS = 233 / 8
+# VALU instructions per (sample, frequency) pair in the one-pass fit step's two
+# loops, counted in the gfx950 assembly: 180 per 8 pairs (forward, two samples
+# per lane) and 217 per 8 (adjoint, each sample's product r t read with it from
+# LDS instead of formed per pair).  The separate forward and adjoint kernels
+# take 89 per 4 and 233 per 8.
+SINUSOID_FIT_OPS = (180 / 8, 217 / 8)
 
 
 def bench_ragged(torch, reps, plain_gbs, x_host):
@@ -486,7 +488,7 @@ def bench_sinusoid(torch, reps):
         return 0.5 * torch.dot(rr, rr), S @ rr, A * (C @ (rr * t)), A * (C @ rr)
     c_ms, _ = time_launches(torch, composed, reps, 2, ALU_WARM_MS)
     pairs = N * K
-    ops = pairs * (SINUSOID_FWD_OPS + SINUSOID_ADJ_OPS)
+    ops = pairs * sum(SINUSOID_FIT_OPS)
     del theta, S, C
     return {"workload": "y(t) = sum_k A_k sin(w_k t + phi_k), N = %d samples, K = %d, loss "
                         "1/2 sum (y - y_obs)^2, forward + adjoint" % (N, K),
@@ -496,8 +498,7 @@ def bench_sinusoid(torch, reps):
             "composed_plain_kernel_plus_torch_ms":
             round(c_ms, 4), "speedup_vs_composed": round(c_ms / tot_ms, 2),
             "pairs_per_s": round(2 * pairs / (tot_ms * 1e-3), 1),
-            "roofline": alu_roofline(ops / (tot_ms * 1e-3) / 1e12,
-                                     [SINUSOID_FWD_OPS, SINUSOID_ADJ_OPS], ceil)}
+            "roofline": alu_roofline(ops / (tot_ms * 1e-3) / 1e12, list(SINUSOID_FIT_OPS), ceil)}
 
 
 def bench_interleaved(torch, reps, plain_gbs, x_host):

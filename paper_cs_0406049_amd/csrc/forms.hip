@@ -431,12 +431,14 @@ __global__ void __launch_bounds__(256) k_sinusoid_reduce(const float *partial, i
 // K5b: one step of the least-squares fit in one pass over the samples.  A
 // workgroup of kAdjWaves waves owns kAdjWaves * kAdjChunk consecutive
 // samples.  Phase 1, lane <-> sample: y_i as the forward model computes it,
-// r_i = y_i - y_obs_i, kept in LDS with t_i (the residual never goes to
-// HBM), and the workgroup's partial of sum r_i^2.  Phase 2, lane <->
-// frequency: exactly the adjoint kernel's sums over the same chunks in the
-// same order, with t_i and r_i read from LDS, and the same tree over the
-// waves.  The gradients are therefore the same bits as the forward kernel's
-// residual followed by the adjoint kernel.
+// r_i = y_i - y_obs_i, kept in LDS as (t_i, r_i, r_i t_i) (the residual
+// never goes to HBM), and the workgroup's partial of sum r_i^2.  Phase 2,
+// lane <-> frequency: exactly the adjoint kernel's sums over the same chunks
+// in the same order, each sample one LDS read, its product r_i t_i rounded
+// once per sample instead of once per frequency (the same value the adjoint
+// kernel rounds per pair), and the same tree over the waves.  The gradients
+// are therefore the same bits as the forward kernel's residual followed by
+// the adjoint kernel.
 constexpr int kFitSamples = kAdjWaves * (int)kAdjChunk;  // 2048
 
 __global__ void __launch_bounds__(64 * kAdjWaves) k_sinusoid_fit(
@@ -444,8 +446,7 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_sinusoid_fit(
     const float *__restrict__ A, const float *__restrict__ w, const float *__restrict__ phi,
     int32_t K, int32_t kgroups, float *partial, float *loss_part)
 {
-    __shared__ float ts[kFitSamples];
-    __shared__ float rs[kFitSamples];
+    __shared__ f4 samp[kFitSamples];  // (t, r, r t, unused) per sample
     __shared__ float sums[3][kAdjWaves][64];
     __shared__ float red[64 * kAdjWaves];
     const int64_t base = (int64_t)blockIdx.x * kFitSamples;
@@ -482,8 +483,7 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_sinusoid_fit(
             r = acc[h] - y_obs[i];
             sq = __builtin_fmaf(r, r, sq);
         }
-        ts[li] = ti[h];
-        rs[li] = r;
+        samp[li] = f4{ti[h], r, r * ti[h], 0.0f};
     }
     red[threadIdx.x] = sq;
     __syncthreads();
@@ -498,8 +498,8 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_sinusoid_fit(
     // phase 2: the adjoint sums, one k group of 64 frequencies at a time
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t i0 = base + (int64_t)wave * kAdjChunk;
-    const int64_t i1 = min(i0 + kAdjChunk, N);
+    const int32_t j0 = wave * (int32_t)kAdjChunk;  // this wave's samples, block-local
+    const int32_t j1 = (int32_t)min<int64_t>(j0 + kAdjChunk, N - base);
     for (int32_t kg = 0; kg < kgroups; ++kg) {
         const int32_t k = kg * 64 + lane;
         const bool active = k < K;
@@ -507,13 +507,13 @@ __global__ void __launch_bounds__(64 * kAdjWaves) k_sinusoid_fit(
         const float pk = active ? phi[k] : 0.f;
         float sa = 0.f, sp = 0.f, sw = 0.f;
 #pragma unroll 8
-        for (int64_t i = i0; i < i1; ++i) {
-            const float ti = ts[i - base], gi = rs[i - base];
+        for (int32_t j = j0; j < j1; ++j) {
+            const f4 q = samp[j];  // one LDS read: t, r and the product r t
             float sv, cv;
-            sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(wk, ti, pk), sv, cv);
-            sa = __builtin_fmaf(gi, sv, sa);
-            sp = __builtin_fmaf(gi, cv, sp);
-            sw = __builtin_fmaf(gi * ti, cv, sw);
+            sincos_pair<Arith::Fused, Method::Normalized>(__builtin_fmaf(wk, q.x, pk), sv, cv);
+            sa = __builtin_fmaf(q.y, sv, sa);
+            sp = __builtin_fmaf(q.y, cv, sp);
+            sw = __builtin_fmaf(q.z, cv, sw);
         }
         if (kg > 0)
             __syncthreads();  // the previous group's tree has read sums
