@@ -601,15 +601,20 @@ def bench_serve(torch, plain_gelem_s):
     out = {"workload": "%d requests, sizes log-uniform in [1e3, 1e7] (seed 4, mean %.0f), "
                        "Poisson arrivals at 70%% of the plain kernel's rate (%.0f req/s), "
                        "budget 8 GiB, inputs resident in HBM" % (rs.sizes.size, mean_n, rate)}
-    # the batched server with its defaults (size split at 2^21 elements), the
-    # same without the split, and one plain launch per request; the open-loop
-    # replay at 70 % load is repeated SERVE_REPLAYS times on one server, and
-    # the median and range of each run's p50 and p99 are reported
-    for name, mode, split in (("batched", serve.MODE_BATCHED, 0),
-                              ("batched_no_size_split", serve.MODE_BATCHED, -1),
-                              ("per_request", serve.MODE_PER_REQUEST, 0)):
+    # the batched server with its defaults (size split at 2^21 elements, each
+    # class's batches in order on its own stream), the same with every batch
+    # on its slot's stream, that without the split, and one plain launch per
+    # request; the open-loop replay at 70 % load is repeated SERVE_REPLAYS
+    # times on one server, and the median and range of each run's p50 and p99
+    # are reported
+    for name, mode, split, per_slot in (("batched", serve.MODE_BATCHED, 0, False),
+                                        ("batched_stream_per_slot", serve.MODE_BATCHED, 0, True),
+                                        ("batched_no_size_split", serve.MODE_BATCHED, -1, True),
+                                        ("per_request", serve.MODE_PER_REQUEST, 0, True)):
         replays = SERVE_REPLAYS if mode == serve.MODE_BATCHED else 1
-        with serve.Server(mode=mode, max_inflight=4, auto_release=True, split_elems=split) as srv:
+        cfg = dict(mode=mode, max_inflight=4, auto_release=True, split_elems=split,
+                   stream_per_slot=per_slot)
+        with serve.Server(**cfg) as srv:
             srv.replay(xs[:200], rs.sizes[:200], np.zeros(200, np.int64))   # warm
             runs = []
             for _ in range(replays):
@@ -631,7 +636,7 @@ def bench_serve(torch, plain_gelem_s):
                     summ[key + "_range"] = [round(vals[0], 3), round(vals[-1], 3)]
                 summ["replays"] = replays
         closed = None
-        with serve.Server(mode=mode, max_inflight=4, auto_release=True, split_elems=split) as srv:
+        with serve.Server(**cfg) as srv:
             comp = srv.replay(xs, rs.sizes, np.zeros(rs.sizes.size, np.int64))
             closed = serve.latency_summary(comp)
         summ["saturation_gelem_s"] = round(closed["throughput_gelem_s"], 2)

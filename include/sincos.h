@@ -417,7 +417,11 @@ SINCOS_API int sincos_f32_doublings(const float *x, float *s, float *c, int64_t 
  * size split, requests of more than split_elems elements and smaller ones
  * never share a batch: the oldest waiting request decides the class, and
  * the batch takes the waiting requests of that class in arrival order, so a
- * small request never waits for a large one's batch to finish.  A completion carries the device addresses of the request's
+ * small request never waits for a large one's batch to finish.  Batches of
+ * one class run one after another on that class's stream, each at the rate
+ * of the whole device, while the other class's stream overlaps them
+ * (stream_per_slot = 1 instead lets every batch in flight share the device).
+ * A completion carries the device addresses of the request's
  * outputs; they stay valid until the request is released (or at once with
  * auto_release).  Release returns the request's budget and arena block.
  * Each result is the same bits as a plain sincos_f32 call on the same input
@@ -443,6 +447,11 @@ typedef struct {
     int32_t auto_release;       /* 1 = free a request's outputs as soon as it completes */
     int64_t split_elems;        /* size split between batch classes (0 = 2^21 elements,
                                    -1 = no split: one class)                            */
+    int32_t stream_per_slot;    /* 0 = the batches of one size class run in order on that
+                                   class's stream, and the classes' streams overlap;
+                                   1 = every batch in flight on a stream of its own, all
+                                   overlapping (mode 1 always runs this way); else EINVAL */
+    int32_t reserved;           /* set to 0                                              */
 } sincos_server_config_t;
 
 typedef struct {

@@ -47,7 +47,8 @@ class ServerConfig(ctypes.Structure):
                 ("arith", ctypes.c_int32), ("method", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("executor", ctypes.c_int32), ("sim_batch_ns", ctypes.c_int64),
                 ("sim_elem_ps", ctypes.c_int64), ("sim_fail_every", ctypes.c_int32),
-                ("auto_release", ctypes.c_int32), ("split_elems", ctypes.c_int64)]
+                ("auto_release", ctypes.c_int32), ("split_elems", ctypes.c_int64),
+                ("stream_per_slot", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Completion(ctypes.Structure):

@@ -8,11 +8,15 @@
 //   3. admits pending requests in arrival order while the head request's
 //      12 n bytes fit in the budget and an arena block for its outputs is
 //      free (no overtaking, so no request starves);
-//   4. if a stream slot is free, sends every admitted, unlaunched request
-//      (up to the batch caps) to the device as one ragged launch (mode 0) or
-//      one request as one plain launch (mode 1).
+//   4. if a slot is free, sends every admitted, unlaunched request of the
+//      oldest one's size class (up to the batch caps) to the device as one
+//      ragged launch (mode 0), or one request as one plain launch (mode 1).
 // Requests that arrive while batches run are admitted as budget frees up and
-// ride in the next batch: up to max_inflight batches overlap on the device.
+// ride in the next batch: up to max_inflight batches are on the device.  By
+// default a batch runs on its size class's stream, behind the earlier
+// batches of that class, so each batch has the device to itself but for the
+// other class's work; with stream_per_slot every slot has its own stream and
+// all batches in flight share the device.
 #include "../../include/sincos.h"
 #include "internal.hpp"
 #include "serve.hpp"
@@ -71,8 +75,13 @@ public:
 
 class GpuExecutor : public Executor {
 public:
-    GpuExecutor(int device, uint64_t arena_bytes, int arith, int method, int mode)
-        : device_(device), arena_bytes_(arena_bytes), arith_(arith), method_(method), mode_(mode)
+    // class_split > 0: one stream per size class (requests of more than
+    // class_split elements form class 1; 0 when there is one class), and a
+    // batch runs on its class's stream; class_split < 0: each slot's stream.
+    GpuExecutor(int device, uint64_t arena_bytes, int arith, int method, int mode,
+                int64_t class_split)
+        : device_(device), arena_bytes_(arena_bytes), arith_(arith), method_(method), mode_(mode),
+          class_split_(class_split)
     {
     }
     ~GpuExecutor() override
@@ -80,6 +89,11 @@ public:
         int prev = -1;
         const bool restore = hipGetDevice(&prev) == hipSuccess && prev != device_;
         (void)hipSetDevice(device_);
+        for (hipStream_t &s : class_streams_)
+            if (s) {
+                (void)hipStreamSynchronize(s);
+                (void)hipStreamDestroy(s);
+            }
         for (auto &sl : slots_) {
             if (sl.stream)
                 (void)hipStreamSynchronize(sl.stream);
@@ -112,20 +126,29 @@ public:
                 hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
                 return set_error(SINCOS_EHIP, "server: cannot create streams and events");
         }
+        if (class_split_ >= 0)
+            for (hipStream_t &s : class_streams_)
+                if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+                    return set_error(SINCOS_EHIP, "server: cannot create the class streams");
         return SINCOS_OK;
     }
     int launch(int slot, const std::vector<Request *> &batch) override
     {
         Slot &sl = slots_[slot];
+        // the batch's stream: its class's (batches of a class run in order), or the slot's
+        const hipStream_t st =
+            class_split_ < 0 ? sl.stream
+                             : class_streams_[class_split_ > 0 && batch.front()->n > class_split_];
+        sl.used = st;
         const LaunchShape shape = default_shape(mode_ == 1 ? kFormPlain : kFormRagged);
         int rc = SINCOS_OK;
         for (Request *r : batch)  // inputs produced on the submitters' streams
-            if (r->ready && hipStreamWaitEvent(sl.stream, r->ready, 0) != hipSuccess)
+            if (r->ready && hipStreamWaitEvent(st, r->ready, 0) != hipSuccess)
                 return set_error(SINCOS_EHIP, "server: cannot wait for a request's input");
         if (mode_ == 1) {
             for (Request *r : batch) {
                 hipError_t e = launch_sincos(r->x, r->s, r->c, r->n, arith_, method_,
-                                             resolve_plain_shape(shape, r->n, *dev_), sl.stream);
+                                             resolve_plain_shape(shape, r->n, *dev_), st);
                 if (e != hipSuccess)
                     return set_error(SINCOS_EHIP, std::string("server: ") + hipGetErrorString(e));
             }
@@ -137,17 +160,17 @@ public:
                 table_add(table_, r->x, r->s, r->c, r->n, shape);
             if (table_.desc.size() <= (size_t)kInlineSegs) {
                 // small batch: the table travels in the kernel arguments
-                rc = launch_table_inline(table_, arith_, method_, shape, *dev_, sl.stream);
+                rc = launch_table_inline(table_, arith_, method_, shape, *dev_, st);
             } else {
                 rc = grow_staging(sl.staging, staged_bytes(table_));
                 if (rc == SINCOS_OK)
                     rc = stage_and_launch(table_, sl.staging.host, sl.staging.dev, arith_,
-                                          method_, shape, *dev_, sl.stream);
+                                          method_, shape, *dev_, st);
             }
             if (rc != SINCOS_OK)
                 return rc;
         }
-        if (hipEventRecord(sl.done, sl.stream) != hipSuccess)
+        if (hipEventRecord(sl.done, st) != hipSuccess)
             return set_error(SINCOS_EHIP, "server: event record failed");
         return SINCOS_OK;
     }
@@ -161,18 +184,25 @@ public:
         return SINCOS_EHIP;
     }
     void wait(int slot) override { (void)hipEventSynchronize(slots_[slot].done); }
-    void drain(int slot) override { (void)hipStreamSynchronize(slots_[slot].stream); }
+    void drain(int slot) override
+    {
+        const Slot &sl = slots_[slot];
+        (void)hipStreamSynchronize(sl.used ? sl.used : sl.stream);
+    }
     char *arena_base() override { return arena_; }
 
 private:
     struct Slot {
         hipStream_t stream = nullptr;
+        hipStream_t used = nullptr;  // the stream of the slot's last batch
         hipEvent_t done = nullptr;
         StagingBuffers staging;  // reused only after the slot's batch finished
     };
     int device_;
     uint64_t arena_bytes_;
     int arith_, method_, mode_;
+    int64_t class_split_;
+    hipStream_t class_streams_[2] = {nullptr, nullptr};
     const DeviceInfo *dev_ = nullptr;
     char *arena_ = nullptr;
     std::vector<Slot> slots_;
@@ -515,6 +545,8 @@ extern "C" int sincos_server_create(const sincos_server_config_t *cfg, sincos_se
         return set_error(SINCOS_EINVAL, "server_create: mode must be 0 or 1");
     if (c.executor != 0 && c.executor != 1)
         return set_error(SINCOS_EINVAL, "server_create: executor must be 0 or 1");
+    if (c.stream_per_slot != 0 && c.stream_per_slot != 1)
+        return set_error(SINCOS_EINVAL, "server_create: stream_per_slot must be 0 or 1");
     auto srv = std::make_unique<sincos_server>();
     srv->cfg = c;
     srv->budget = (uint64_t)c.budget_bytes;
@@ -527,8 +559,10 @@ extern "C" int sincos_server_create(const sincos_server_config_t *cfg, sincos_se
     if (c.executor == 0) {
         if (hipGetDevice(&srv->device) != hipSuccess)
             return set_error(SINCOS_ENODEV, "server_create: no HIP device");
+        const int64_t class_split =
+            c.mode == 1 || c.stream_per_slot ? -1 : std::max<int64_t>(c.split_elems, 0);
         srv->exec = std::make_unique<GpuExecutor>(srv->device, srv->arena.capacity(), c.arith,
-                                                  c.method, c.mode);
+                                                  c.method, c.mode, class_split);
     } else {
         srv->exec = std::make_unique<SimExecutor>(c.sim_batch_ns, c.sim_elem_ps, c.sim_fail_every);
     }

@@ -36,11 +36,12 @@ class Server:
                  arith: int = _capi.ARITH_FUSED, method: int = _capi.METHOD_NORMALIZED,
                  mode: int = MODE_BATCHED, executor: int = EXEC_GPU, sim_batch_ns: int = 0,
                  sim_elem_ps: int = 0, sim_fail_every: int = 0, auto_release: bool = False,
-                 split_elems: int = 0):
+                 split_elems: int = 0, stream_per_slot: bool = False):
         cfg = _capi.ServerConfig(int(budget_bytes), int(max_inflight), int(max_batch_requests),
                                  int(max_batch_elems), int(arith), int(method), int(mode),
                                  int(executor), int(sim_batch_ns), int(sim_elem_ps),
-                                 int(sim_fail_every), int(bool(auto_release)), int(split_elems))
+                                 int(sim_fail_every), int(bool(auto_release)), int(split_elems),
+                                 int(bool(stream_per_slot)), 0)
         h = ctypes.c_void_p()
         _capi._check(_capi.lib().sincos_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -22,8 +22,12 @@ def _pool(torch, elems, seed):
     return xh, torch.from_numpy(xh).cuda()
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_mix_equals_alone(torch_dev, mode):
+@pytest.mark.parametrize("mode,stream_per_slot,split", [
+    (0, False, 0),        # the default: each size class's batches in order on its stream
+    (0, False, 4096),     # both classes present, on two streams
+    (0, True, 4096),      # every batch on its slot's stream
+    (1, True, 0)])        # one plain launch per request
+def test_mix_equals_alone(torch_dev, mode, stream_per_slot, split):
     torch = torch_dev
     from paper_cs_0406049_amd import _capi, serve
     xh, pool = _pool(torch, 1 << 22, 1)
@@ -33,7 +37,8 @@ def test_mix_equals_alone(torch_dev, mode):
     offs[::5] += rng.integers(1, 4, offs[::5].size)   # some inputs off the 16-byte grid
     assert np.all(offs >= 0) and np.all(offs + sizes <= pool.numel())
     base = pool.data_ptr()
-    with serve.Server(max_inflight=3, mode=mode) as srv:
+    with serve.Server(max_inflight=3, mode=mode, stream_per_slot=stream_per_slot,
+                      split_elems=split) as srv:
         ids = [srv.submit(base + 4 * int(o), int(n), tag=j) for j, (o, n) in enumerate(zip(offs, sizes))]
         comps = []
         while len(comps) < len(ids):
@@ -57,8 +62,8 @@ def test_mix_equals_alone(torch_dev, mode):
                 assert_bit_exact(s_mix.cpu().numpy(), so, "served sin %d" % j)
                 assert_bit_exact(c_mix.cpu().numpy(), co, "served cos %d" % j)
             srv.release(c.id)
-        log("mode %d: %d requests in %d batches, inflight peak %d" % (
-            mode, st["completed"], st["batches"], st["inflight_peak"]))
+        log("mode %d, stream per slot %d, split %d: %d requests in %d batches, inflight peak %d"
+            % (mode, stream_per_slot, split, st["completed"], st["batches"], st["inflight_peak"]))
         assert srv.stats()["budget_in_use"] == 0
 
 

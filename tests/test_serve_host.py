@@ -1,6 +1,7 @@
 """The request server's scheduling on the host, with the simulated executor
 (no device work): admission by budget, arrival order, continuous batching
 and overlap, latency accounting, failure and shutdown paths."""
+import ctypes
 import time
 
 import numpy as np
@@ -38,6 +39,11 @@ def test_config_validation():
         with pytest.raises(_capi.SincosError) as e:
             sim(**bad)
         assert e.value.status == _capi.EINVAL
+    # stream_per_slot takes 0 or 1 only (the binding passes a bool)
+    cfg = _capi.ServerConfig(executor=serve.EXEC_SIM, stream_per_slot=2)
+    h = ctypes.c_void_p()
+    assert _capi.lib().sincos_server_create(ctypes.byref(cfg), ctypes.byref(h)) == _capi.EINVAL
+    assert not h.value
 
 
 def test_submit_validation_and_budget_reject():
