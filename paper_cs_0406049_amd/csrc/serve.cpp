@@ -121,8 +121,9 @@ public:
             return set_error(SINCOS_ENOMEM, "server: cannot allocate the output arena");
         }
         slots_.resize(slots);
-        for (auto &sl : slots_) {
-            if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+        for (auto &sl : slots_) {  // a stream per slot only where batches run on it
+            if ((class_split_ < 0 &&
+                 hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) ||
                 hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
                 return set_error(SINCOS_EHIP, "server: cannot create streams and events");
         }
@@ -187,7 +188,8 @@ public:
     void drain(int slot) override
     {
         const Slot &sl = slots_[slot];
-        (void)hipStreamSynchronize(sl.used ? sl.used : sl.stream);
+        if (sl.used)  // set by the slot's last launch
+            (void)hipStreamSynchronize(sl.used);
     }
     char *arena_base() override { return arena_; }
 
