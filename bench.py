@@ -601,7 +601,7 @@ def bench_serve(torch, plain_gelem_s):
     out = {"workload": "%d requests, sizes log-uniform in [1e3, 1e7] (seed 4, mean %.0f), "
                        "Poisson arrivals at 70%% of the plain kernel's rate (%.0f req/s), "
                        "budget 8 GiB, inputs resident in HBM" % (rs.sizes.size, mean_n, rate)}
-    # the batched server with its defaults (size split at 2^21 elements, each
+    # the batched server with its defaults (size split at 2^22 elements, each
     # class's batches in order on its own stream), the same with every batch
     # on its slot's stream, that without the split, and one plain launch per
     # request; the open-loop replay at 70 % load is repeated SERVE_REPLAYS

@@ -445,7 +445,7 @@ typedef struct {
     int64_t sim_elem_ps;        /* simulated: picoseconds per element                   */
     int32_t sim_fail_every;     /* simulated: every k-th batch fails (0 = never)        */
     int32_t auto_release;       /* 1 = free a request's outputs as soon as it completes */
-    int64_t split_elems;        /* size split between batch classes (0 = 2^21 elements,
+    int64_t split_elems;        /* size split between batch classes (0 = 2^22 elements,
                                    -1 = no split: one class)                            */
     int32_t stream_per_slot;    /* 0 = the batches of one size class run in order on that
                                    class's stream, and the classes' streams overlap;

@@ -532,7 +532,7 @@ extern "C" int sincos_server_create(const sincos_server_config_t *cfg, sincos_se
         c.split_elems < -1)
         return set_error(SINCOS_EINVAL, "server_create: negative setting");
     if (c.split_elems == 0)
-        c.split_elems = int64_t(1) << 21;
+        c.split_elems = int64_t(1) << 22;
     if (c.budget_bytes == 0)
         c.budget_bytes = int64_t(8) << 30;
     if (c.max_inflight == 0)
