@@ -587,7 +587,7 @@ def bench_huygens(torch, reps):
                                  tops * HUYGENS_SLOTS / HUYGENS_OPS / VALU_PEAK_TOPS, 4))}
 
 
-def bench_serve(torch, plain_gelem_s):
+def bench_serve(torch, plain_gelem_s, only=None):
     import numpy as np
     from paper_cs_0406049_amd import serve, workloads
     rs = workloads.request_stream()
@@ -604,47 +604,73 @@ def bench_serve(torch, plain_gelem_s):
     # the batched server with its defaults (size split at 2^22 elements, each
     # class's batches in order on its own stream), the same with every batch
     # on its slot's stream, that without the split, and one plain launch per
-    # request; the open-loop replay at 70 % load is repeated SERVE_REPLAYS
-    # times on one server, and the median and range of each run's p50 and p99
-    # are reported
-    for name, mode, split, per_slot in (("batched", serve.MODE_BATCHED, 0, False),
-                                        ("batched_stream_per_slot", serve.MODE_BATCHED, 0, True),
-                                        ("batched_no_size_split", serve.MODE_BATCHED, -1, True),
-                                        ("per_request", serve.MODE_PER_REQUEST, 0, True)):
-        replays = SERVE_REPLAYS if mode == serve.MODE_BATCHED else 1
-        cfg = dict(mode=mode, max_inflight=4, auto_release=True, split_elems=split,
-                   stream_per_slot=per_slot)
-        with serve.Server(**cfg) as srv:
-            srv.replay(xs[:200], rs.sizes[:200], np.zeros(200, np.int64))   # warm
-            runs = []
-            for _ in range(replays):
-                comp = srv.replay(xs, rs.sizes, arr)
-                one = serve.latency_summary(comp)
-                # where the time goes: waiting to be launched, then on the device
-                one["p50_submit_to_launch_us"] = float(
-                    np.percentile((comp["t_launch_ns"] - comp["t_submit_ns"]) / 1e3, 50))
-                one["p50_launch_to_complete_us"] = float(
-                    np.percentile((comp["t_complete_ns"] - comp["t_launch_ns"]) / 1e3, 50))
-                runs.append(one)
-            runs_by_p99 = sorted(runs, key=lambda r: r["p99_us"])
-            summ = dict(runs_by_p99[len(runs) // 2])
-            summ["batches"] = srv.stats()["batches"] // (replays + 1)
-            if replays > 1:
-                for key in ("p50_us", "p99_us"):
-                    vals = sorted(r[key] for r in runs)
-                    summ[key + "_median"] = float(np.median(vals))
-                    summ[key + "_range"] = [round(vals[0], 3), round(vals[-1], 3)]
-                summ["replays"] = replays
-        closed = None
+    # request.  The batched servers run side by side and take turns: each
+    # round replays the 70 % load once on each (order alternating), so drift
+    # over the run falls on all alike; SERVE_REPLAYS rounds, and the median
+    # and range of each server's p50 and p99 are reported
+    variants = (("batched", serve.MODE_BATCHED, 0, False),
+                ("batched_stream_per_slot", serve.MODE_BATCHED, 0, True),
+                ("batched_no_size_split", serve.MODE_BATCHED, -1, True))
+    if only:
+        unknown = set(only) - {v[0] for v in variants}
+        if unknown:
+            raise SystemExit("unknown serve variants: %s" % ", ".join(sorted(unknown)))
+        variants = tuple(v for v in variants if v[0] in only)
+
+    def one_run(comp):
+        one = serve.latency_summary(comp)
+        # where the time goes: waiting to be launched, then on the device
+        one["p50_submit_to_launch_us"] = float(
+            np.percentile((comp["t_launch_ns"] - comp["t_submit_ns"]) / 1e3, 50))
+        one["p50_launch_to_complete_us"] = float(
+            np.percentile((comp["t_complete_ns"] - comp["t_launch_ns"]) / 1e3, 50))
+        return one
+
+    def saturation(cfg):
         with serve.Server(**cfg) as srv:
             comp = srv.replay(xs, rs.sizes, np.zeros(rs.sizes.size, np.int64))
-            closed = serve.latency_summary(comp)
-        summ["saturation_gelem_s"] = round(closed["throughput_gelem_s"], 2)
-        summ["saturation_per_byte_vs_plain"] = round(closed["throughput_gelem_s"] / plain_gelem_s, 4)
+            return serve.latency_summary(comp)["throughput_gelem_s"]
+
+    cfgs = {name: dict(mode=mode, max_inflight=4, auto_release=True, split_elems=split,
+                       stream_per_slot=per_slot) for name, mode, split, per_slot in variants}
+    servers = {name: serve.Server(**cfg) for name, cfg in cfgs.items()}
+    runs = {name: [] for name in servers}
+    batches = {}
+    try:
+        for srv in servers.values():
+            srv.replay(xs[:200], rs.sizes[:200], np.zeros(200, np.int64))   # warm
+        names = list(servers)
+        for rnd in range(SERVE_REPLAYS):
+            for name in (names if rnd % 2 == 0 else names[::-1]):
+                runs[name].append(one_run(servers[name].replay(xs, rs.sizes, arr)))
+        for name, srv in servers.items():
+            batches[name] = srv.stats()["batches"] // (SERVE_REPLAYS + 1)
+    finally:
+        for srv in servers.values():
+            srv.close()
+    cfgs["per_request"] = dict(mode=serve.MODE_PER_REQUEST, max_inflight=4, auto_release=True,
+                               stream_per_slot=True)
+    with serve.Server(**cfgs["per_request"]) as srv:
+        srv.replay(xs[:200], rs.sizes[:200], np.zeros(200, np.int64))   # warm
+        runs["per_request"] = [one_run(srv.replay(xs, rs.sizes, arr))]
+        batches["per_request"] = srv.stats()["batches"] // 2
+    for name, rr in runs.items():
+        runs_by_p99 = sorted(rr, key=lambda r: r["p99_us"])
+        summ = dict(runs_by_p99[len(rr) // 2])
+        summ["batches"] = batches[name]
+        if len(rr) > 1:
+            for key in ("p50_us", "p99_us"):
+                vals = sorted(r[key] for r in rr)
+                summ[key + "_median"] = float(np.median(vals))
+                summ[key + "_range"] = [round(vals[0], 3), round(vals[-1], 3)]
+            summ["replays"] = len(rr)
+        sat = saturation(cfgs[name])
+        summ["saturation_gelem_s"] = round(sat, 2)
+        summ["saturation_per_byte_vs_plain"] = round(sat / plain_gelem_s, 4)
         out[name] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in summ.items()}
         log("serve %s: p50 %.1f us, p99 %.1f us (median of %d), %.1f Gelem/s delivered, "
             "saturation %.1f" % (name, summ.get("p50_us_median", summ["p50_us"]),
-                                 summ.get("p99_us_median", summ["p99_us"]), replays,
+                                 summ.get("p99_us_median", summ["p99_us"]), len(rr),
                                  summ["throughput_gelem_s"], summ["saturation_gelem_s"]))
     return out
 
@@ -669,6 +695,10 @@ def main(argv=None):
     ap.add_argument("--forms",
                     default="variants,ablations,ragged,interleaved,adjoint,sinusoid,huygens,serve",
                     help="comma list of forms to measure after the plain kernel ('' = none)")
+    ap.add_argument("--serve-variants", default="",
+                    help="comma list of the batched servers the serve form measures "
+                         "(batched, batched_stream_per_slot, batched_no_size_split; '' = all); "
+                         "one plain launch per request is always measured")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -791,7 +821,8 @@ def main(argv=None):
         elif f == "huygens":
             out["forms"]["huygens"] = bench_huygens(torch, max(10, args.steps // 5))
         elif f == "serve":
-            out["forms"]["serve"] = bench_serve(torch, value)
+            out["forms"]["serve"] = bench_serve(
+                torch, value, [v for v in args.serve_variants.split(",") if v] or None)
         torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
     return 0
