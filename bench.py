@@ -633,10 +633,12 @@ def bench_serve(torch, plain_gelem_s, only=None):
 
     cfgs = {name: dict(mode=mode, max_inflight=4, auto_release=True, split_elems=split,
                        stream_per_slot=per_slot) for name, mode, split, per_slot in variants}
-    servers = {name: serve.Server(**cfg) for name, cfg in cfgs.items()}
-    runs = {name: [] for name in servers}
+    servers = {}
+    runs = {name: [] for name in cfgs}
     batches = {}
     try:
+        for name, cfg in cfgs.items():
+            servers[name] = serve.Server(**cfg)
         for srv in servers.values():
             srv.replay(xs[:200], rs.sizes[:200], np.zeros(200, np.int64))   # warm
         names = list(servers)
